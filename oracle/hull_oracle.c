@@ -1,0 +1,555 @@
+/*
+ * CPU oracle for proton-CT hull detection (Schultze, Witt, Censor, Schulte,
+ * Schubert, "Performance of Hull-Detection Algorithms for Proton Computed
+ * Tomography Reconstruction", arXiv:1402.1720).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark call this library. It shares no source, header,
+ * table or constant with the GPU library, and the GPU library never calls it.
+ *
+ * What it computes, in the paper's order:
+ *   1. Classification (Section 3.2, eq. for I_L; Section 3.4, eq. for I_H):
+ *      low  <=> WEPL <  E_L,   high <=> WEPL > E_H   (FP32 compares).
+ *   2. Straight line per history (Sections 3.2-3.4: L_i joins the entry and
+ *      exit points), moved into the object frame: the object turns by theta
+ *      in front of a fixed horizontal beam (Section 2.2), so object = R(-theta)
+ *      * lab. FP32 arithmetic, one rounding per operation, then the endpoints
+ *      are rounded to 1/1024 voxel.
+ *   3. The voxel set A_i = { v : d(L_i, v) <= d0 } (Sections 3.2 and 3.4).
+ *      Reading: d0 = 0 against half-open voxel boxes, L_i the infinite line;
+ *      v is in A_i iff some point of the line lies in [v, v+1) on every axis
+ *      (in voxel units). The membership test below decides this exactly with
+ *      integer arithmetic; it is the test of Algorithms 1-3's inner loop.
+ *   4. Counts N(v) = |C(v)| over low histories (Section 3.3) and M(v) over
+ *      high histories (Section 3.4).
+ *   5. Hull rules: SC  H1 = V minus the union of A_i (Section 3.2),
+ *      MSC H2 by the neighbour-difference rule (Section 3.3) or a plain count
+ *      threshold, SM H3 = {M > M_t} with M_t from Algorithm 3's maximum slope
+ *      or from a fraction of max M (Section 3.4).
+ *   6. FDK cone-beam FBP hull (Section 3.1): bin, cosine weight, Shepp-Logan
+ *      filter, weighted backprojection, threshold RSP >= 0.6. FP64 throughout,
+ *      except that the bin a history falls in is decided in FP32.
+ *
+ * Every function here is pinned by the test suite to something other than
+ * itself (brute force with exact fractions, hand-derived cases, closed forms,
+ * invariants); none is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_ABI 1
+
+/* Status of one history's geometry. */
+enum { OR_OK = 0, OR_SKIP_NONFINITE = 1, OR_SKIP_RANGE = 2, OR_SKIP_DEGENERATE = 3 };
+
+/* Fixed-point fraction of the quantised endpoints: 1/1024 voxel. */
+#define OR_QBITS 10
+#define OR_QONE 1024
+/* Endpoints further than 2^16 voxels from the grid origin are rejected. */
+#define OR_GMAX 65536.0f
+
+typedef struct {
+    int32_t nx, ny, nz;
+    float dx, dy, dz;
+    float x0, y0, z0; /* lower corner of voxel (0,0,0), object frame, mm */
+} or_grid;
+
+typedef struct {
+    const float *x_in, *y_in, *z_in, *x_out, *y_out, *z_out, *angle_deg, *wepl;
+    int64_t n;
+} or_hist;
+
+typedef struct {
+    int64_t n_low, n_high, n_skipped, n_missed_grid, n_visits_low, n_visits_high;
+} or_stats;
+
+typedef struct {
+    float src_dist_mm, du_mm, dv_mm, u0_mm, v0_mm;
+    int32_t nu, nv, n_angles;
+    float angle0_deg, dangle_deg;
+    int32_t filter; /* 0 = Shepp-Logan */
+    float threshold;
+} or_fbp_params;
+
+int or_abi(void) { return OR_ABI; }
+
+/* ------------------------------------------------------------------------ */
+/* Step 2: object-frame endpoints, rounded to 1/1024 voxel.                  */
+
+/* cos/sin of an angle in degrees: exact remainder modulo 360 in FP64, FP64
+ * libm cos/sin, then rounded to FP32. */
+static void or_trig(float angle_deg, float *c, float *s)
+{
+    const double th = (double)angle_deg;
+    const double r = th - 360.0 * floor(th / 360.0);
+    const double rad = r * 0.017453292519943295;
+    *c = (float)cos(rad);
+    *s = (float)sin(rad);
+}
+
+void or_trig_table(const float *angle_deg, int64_t n, float *c, float *s)
+{
+    for (int64_t i = 0; i < n; ++i) or_trig(angle_deg[i], &c[i], &s[i]);
+}
+
+static int or_point(float c, float s, float x, float y, float z, const or_grid *g, int32_t q[3])
+{
+    /* object frame = lab frame rotated by -theta about z */
+    const float xo = c * x + s * y;
+    const float yo = c * y - s * x;
+    const float zo = z;
+    /* voxel units with a once-rounded reciprocal of the voxel size */
+    const float gx = (xo - g->x0) * (1.0f / g->dx);
+    const float gy = (yo - g->y0) * (1.0f / g->dy);
+    const float gz = (zo - g->z0) * (1.0f / g->dz);
+    if (!(fabsf(gx) < OR_GMAX && fabsf(gy) < OR_GMAX && fabsf(gz) < OR_GMAX)) return OR_SKIP_RANGE;
+    q[0] = (int32_t)rintf(gx * (float)OR_QONE);
+    q[1] = (int32_t)rintf(gy * (float)OR_QONE);
+    q[2] = (int32_t)rintf(gz * (float)OR_QONE);
+    return OR_OK;
+}
+
+int or_quantize(const or_hist *h, const or_grid *g, int64_t i, int32_t qin[3], int32_t qout[3])
+{
+    const float f[8] = {h->x_in[i], h->y_in[i], h->z_in[i], h->x_out[i],
+                        h->y_out[i], h->z_out[i], h->angle_deg[i], h->wepl[i]};
+    for (int k = 0; k < 8; ++k)
+        if (!isfinite(f[k])) return OR_SKIP_NONFINITE;
+    float c, s;
+    or_trig(f[6], &c, &s);
+    int st = or_point(c, s, f[0], f[1], f[2], g, qin);
+    if (st == OR_OK) st = or_point(c, s, f[3], f[4], f[5], g, qout);
+    if (st != OR_OK) return st;
+    if (qin[0] == qout[0] && qin[1] == qout[1] && qin[2] == qout[2]) return OR_SKIP_DEGENERATE;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 3: v in A_i, decided exactly.                                        */
+
+/* The line is P(t) = P0 + t*D in units of 1/1024 voxel. On a moving axis the
+ * points with 1024 v <= P(t) < 1024 (v+1) form one t-interval whose ends are
+ * fractions; on a fixed axis the coordinate is in the slab or not. A family of
+ * intervals on the real line meets iff every pair meets (Helly's theorem in one
+ * dimension), so the test compares every lower end with every upper end. */
+int or_line_meets_cell(const int64_t P0[3], const int64_t D[3], const int32_t v[3])
+{
+    int64_t ln[3], ld[3], un[3], ud[3];
+    int lc[3], uc[3], na = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t lo = (int64_t)OR_QONE * v[a] - P0[a]; /* P(t)_a = 1024 v     at t = lo / D */
+        const int64_t hi = lo + OR_QONE;                    /* P(t)_a = 1024 v + 1024 at t = hi / D */
+        if (D[a] == 0) {
+            if (!(lo <= 0 && 0 < hi)) return 0;
+            continue;
+        }
+        if (D[a] > 0) { /* t in [lo/D, hi/D) */
+            ln[na] = lo; ld[na] = D[a]; lc[na] = 1;
+            un[na] = hi; ud[na] = D[a]; uc[na] = 0;
+        } else {        /* t in (hi/D, lo/D], written with positive denominators */
+            ln[na] = -hi; ld[na] = -D[a]; lc[na] = 0;
+            un[na] = -lo; ud[na] = -D[a]; uc[na] = 1;
+        }
+        ++na;
+    }
+    for (int a = 0; a < na; ++a)
+        for (int b = 0; b < na; ++b) {
+            if (a == b) continue;
+            const __int128 L = (__int128)ln[a] * ud[b];
+            const __int128 U = (__int128)un[b] * ld[a];
+            if (L > U) return 0;
+            if (L == U && !(lc[a] && uc[b])) return 0;
+        }
+    return 1;
+}
+
+static int or_cmp_i32(const void *a, const void *b)
+{
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Visits every voxel that can possibly be in A_i and keeps those that pass the
+ * exact test. Candidates: the line is cut into the slabs of its major axis m
+ * (largest |D|); inside slab i_m each other coordinate moves between its values
+ * at the two slab faces, so its voxel index lies in [floor(min), floor(max)].
+ * Those ends are computed in FP64 (error far below 1e-6 voxel) and widened by
+ * one voxel each way, so the candidate set contains A_i. If `all` is set every
+ * voxel of the grid is tested instead (Algorithm 1's loop as written).
+ * Writes up to `cap` linear indices (x fastest), sorted, and returns |A_i|. */
+static int64_t or_cells(const int64_t P0[3], const int64_t D[3], const or_grid *g,
+                        int all, int32_t *out, int64_t cap, int32_t *counts)
+{
+    const int32_t n[3] = {g->nx, g->ny, g->nz};
+    int64_t cnt = 0;
+    int32_t v[3];
+    if (all) {
+        for (v[2] = 0; v[2] < n[2]; ++v[2])
+            for (v[1] = 0; v[1] < n[1]; ++v[1])
+                for (v[0] = 0; v[0] < n[0]; ++v[0])
+                    if (or_line_meets_cell(P0, D, v)) {
+                        const int32_t lin = v[0] + n[0] * (v[1] + n[1] * v[2]);
+                        if (out && cnt < cap) out[cnt] = lin;
+                        if (counts) {
+#pragma omp atomic
+                            counts[lin] += 1;
+                        }
+                        ++cnt;
+                    }
+        return cnt;
+    }
+    int m = 0;
+    for (int a = 1; a < 3; ++a)
+        if (llabs(D[a]) > llabs(D[m])) m = a;
+    const int b1 = (m + 1) % 3, b2 = (m + 2) % 3;
+    for (int32_t im = 0; im < n[m]; ++im) {
+        const double t0 = ((double)OR_QONE * im - (double)P0[m]) / (double)D[m];
+        const double t1 = ((double)OR_QONE * (im + 1) - (double)P0[m]) / (double)D[m];
+        int64_t lo[3], hi[3];
+        int empty = 0;
+        const int bs[2] = {b1, b2};
+        for (int k = 0; k < 2; ++k) {
+            const int b = bs[k];
+            const double c0 = ((double)P0[b] + t0 * (double)D[b]) / OR_QONE;
+            const double c1 = ((double)P0[b] + t1 * (double)D[b]) / OR_QONE;
+            int64_t l = (int64_t)floor(fmin(c0, c1)) - 1;
+            int64_t h = (int64_t)floor(fmax(c0, c1)) + 1;
+            if (l < 0) l = 0;
+            if (h > n[b] - 1) h = n[b] - 1;
+            if (l > h) empty = 1;
+            lo[b] = l;
+            hi[b] = h;
+        }
+        if (empty) continue;
+        v[m] = im;
+        for (int64_t j = lo[b1]; j <= hi[b1]; ++j)
+            for (int64_t k = lo[b2]; k <= hi[b2]; ++k) {
+                v[b1] = (int32_t)j;
+                v[b2] = (int32_t)k;
+                if (or_line_meets_cell(P0, D, v)) {
+                    const int32_t lin = v[0] + n[0] * (v[1] + n[1] * v[2]);
+                    if (out && cnt < cap) out[cnt] = lin;
+                    if (counts) {
+#pragma omp atomic
+                        counts[lin] += 1;
+                    }
+                    ++cnt;
+                }
+            }
+    }
+    if (out) qsort(out, (size_t)(cnt < cap ? cnt : cap), sizeof(int32_t), or_cmp_i32);
+    return cnt;
+}
+
+/* A_i for one quantised line: sorted linear indices, returns |A_i|. */
+int64_t or_line_cells(const int32_t qin[3], const int32_t qout[3], const or_grid *g,
+                      int all, int32_t *out, int64_t cap)
+{
+    const int64_t P0[3] = {qin[0], qin[1], qin[2]};
+    const int64_t D[3] = {(int64_t)qout[0] - qin[0], (int64_t)qout[1] - qin[1],
+                          (int64_t)qout[2] - qin[2]};
+    if (D[0] == 0 && D[1] == 0 && D[2] == 0) return 0;
+    return or_cells(P0, D, g, all, out, cap, NULL);
+}
+
+/* counts[v] += |{lines i : v in A_i}| for n quantised lines given as [n][3]. */
+void or_count_lines(const int32_t *qin, const int32_t *qout, int64_t n, const or_grid *g,
+                    int32_t *counts)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t P0[3] = {qin[3 * i], qin[3 * i + 1], qin[3 * i + 2]};
+        const int64_t D[3] = {(int64_t)qout[3 * i] - P0[0], (int64_t)qout[3 * i + 1] - P0[1],
+                              (int64_t)qout[3 * i + 2] - P0[2]};
+        if (D[0] == 0 && D[1] == 0 && D[2] == 0) continue;
+        or_cells(P0, D, g, 0, NULL, 0, counts);
+    }
+}
+
+/* Steps 1-4 over histories [0, n): N counts low histories (WEPL < e_low),
+ * M counts high ones (WEPL > e_high). Either output may be NULL, which also
+ * switches its class off. Counts are added to what N and M hold.
+ * A history with a non-finite field is skipped; so is a history of an active
+ * class whose endpoints leave |g| < 2^16 or coincide after rounding. */
+void or_counts(const or_hist *h, const or_grid *g, float e_low, float e_high,
+               int32_t *N, int32_t *M, or_stats *st)
+{
+    int64_t s_low = 0, s_high = 0, s_skip = 0, s_miss = 0, s_vl = 0, s_vh = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : s_low, s_high, s_skip, s_miss, s_vl, s_vh)
+    for (int64_t i = 0; i < h->n; ++i) {
+        const float f[8] = {h->x_in[i], h->y_in[i], h->z_in[i], h->x_out[i],
+                            h->y_out[i], h->z_out[i], h->angle_deg[i], h->wepl[i]};
+        int finite = 1;
+        for (int k = 0; k < 8; ++k) finite &= isfinite(f[k]) != 0;
+        if (!finite) { ++s_skip; continue; }
+        const float w = h->wepl[i];
+        const int low = N != NULL && w < e_low;
+        const int high = M != NULL && w > e_high;
+        if (!low && !high) continue;
+        int32_t qin[3], qout[3];
+        if (or_quantize(h, g, i, qin, qout) != OR_OK) { ++s_skip; continue; }
+        const int64_t P0[3] = {qin[0], qin[1], qin[2]};
+        const int64_t D[3] = {(int64_t)qout[0] - qin[0], (int64_t)qout[1] - qin[1],
+                              (int64_t)qout[2] - qin[2]};
+        const int64_t c = or_cells(P0, D, g, 0, NULL, 0, low ? N : M);
+        if (low) { ++s_low; s_vl += c; }
+        else { ++s_high; s_vh += c; }
+        if (c == 0) ++s_miss;
+    }
+    if (st) {
+        st->n_low = s_low; st->n_high = s_high; st->n_skipped = s_skip;
+        st->n_missed_grid = s_miss; st->n_visits_low = s_vl; st->n_visits_high = s_vh;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 5: hull rules.                                                       */
+
+enum { OR_MSC_COUNT = 0, OR_MSC_NEIGHBOR_DIFF = 1 };
+enum { OR_SM_FRACTION = 0, OR_SM_MAX_SLOPE = 1 };
+enum { OR_SCOPE_VOLUME = 0, OR_SCOPE_SLICE = 1 };
+enum { OR_NBR_INPLANE4 = 0, OR_NBR_SPATIAL6 = 1 };
+
+/* B(v) = { w : d(v, w) <= 1 } (Section 3.3) read in voxel-index units: v itself
+ * and its face neighbours inside the grid, in the slice (INPLANE4) or in 3-D
+ * (SPATIAL6). Writes up to 7 linear indices, returns how many. */
+static int or_nbrs(const or_grid *g, int nbr, int64_t v, int64_t w[7])
+{
+    const int64_t nx = g->nx, ny = g->ny, nz = g->nz;
+    const int64_t i = v % nx, j = (v / nx) % ny, k = v / (nx * ny);
+    int c = 0;
+    w[c++] = v;
+    if (i > 0) w[c++] = v - 1;
+    if (i < nx - 1) w[c++] = v + 1;
+    if (j > 0) w[c++] = v - nx;
+    if (j < ny - 1) w[c++] = v + nx;
+    if (nbr == OR_NBR_SPATIAL6) {
+        if (k > 0) w[c++] = v - nx * ny;
+        if (k < nz - 1) w[c++] = v + nx * ny;
+    }
+    return c;
+}
+
+/* SC, Algorithm 1: start from all ones and clear every voxel a low line
+ * crosses. With N(v) the number of low lines through v that is H1 = [N == 0]. */
+void or_sc(const int32_t *N, int64_t V, uint8_t *mask)
+{
+    for (int64_t v = 0; v < V; ++v) mask[v] = (uint8_t)(N[v] == 0);
+}
+
+/* MSC. NEIGHBOR_DIFF follows Algorithm 2's final loop: H2(v) starts at 1 and
+ * becomes 0 when some w in B(v) has N(v) - N(w) >= N_t. COUNT keeps v when
+ * N(v) < N_t. Returns 0, or -1 on a bad mode. */
+int or_msc(const int32_t *N, const or_grid *g, int32_t n_t, int mode, int nbr, uint8_t *mask)
+{
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    if (mode == OR_MSC_COUNT) {
+        for (int64_t v = 0; v < V; ++v) mask[v] = (uint8_t)(N[v] < n_t);
+        return 0;
+    }
+    if (mode != OR_MSC_NEIGHBOR_DIFF) return -1;
+    for (int64_t v = 0; v < V; ++v) {
+        int64_t w[7];
+        const int nw = or_nbrs(g, nbr, v, w);
+        mask[v] = 1;
+        for (int k = 0; k < nw; ++k)
+            if ((int64_t)N[v] - (int64_t)N[w[k]] >= n_t) mask[v] = 0;
+    }
+    return 0;
+}
+
+/* SM. MAX_SLOPE follows Algorithm 3: scan v in linear order, w over B(v);
+ * whenever M(v) - M(w) >= MaxSlope, take it as MaxSlope and remember v; then
+ * M_t = M(index) and H3 = [M > M_t]. FRACTION sets H3 = [den*M > num*max M].
+ * With scope SLICE each z-slice gets its own statistic (the paper thresholds
+ * slice by slice, Section 3.4). mt_out (optional) receives M_t per slice (or
+ * once) for MAX_SLOPE and max M for FRACTION. Returns 0 or -1. */
+int or_sm(const int32_t *M, const or_grid *g, int32_t num, int32_t den, int mode, int scope,
+          int nbr, uint8_t *mask, int64_t *mt_out)
+{
+    const int64_t plane = (int64_t)g->nx * g->ny;
+    const int64_t V = plane * g->nz;
+    const int64_t nseg = scope == OR_SCOPE_SLICE ? g->nz : 1;
+    const int64_t seg = scope == OR_SCOPE_SLICE ? plane : V;
+    if (mode != OR_SM_FRACTION && mode != OR_SM_MAX_SLOPE) return -1;
+    if (scope != OR_SCOPE_VOLUME && scope != OR_SCOPE_SLICE) return -1;
+    for (int64_t sgi = 0; sgi < nseg; ++sgi) {
+        const int64_t b = sgi * seg, e = b + seg;
+        if (mode == OR_SM_FRACTION) {
+            int64_t mmax = 0;
+            for (int64_t v = b; v < e; ++v)
+                if (M[v] > mmax) mmax = M[v];
+            for (int64_t v = b; v < e; ++v)
+                mask[v] = (uint8_t)((int64_t)den * M[v] > (int64_t)num * mmax);
+            if (mt_out) mt_out[sgi] = mmax;
+        } else {
+            int64_t max_slope = 0, index = b;
+            for (int64_t v = b; v < e; ++v) {
+                int64_t w[7];
+                const int nw = or_nbrs(g, nbr, v, w);
+                for (int k = 0; k < nw; ++k) {
+                    const int64_t d = (int64_t)M[v] - (int64_t)M[w[k]];
+                    if (d >= max_slope) { max_slope = d; index = v; }
+                }
+            }
+            const int64_t mt = M[index];
+            for (int64_t v = b; v < e; ++v) mask[v] = (uint8_t)(M[v] > mt);
+            if (mt_out) mt_out[sgi] = mt;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 6: FDK hull (Section 3.1). Virtual detector on the lab plane x = 0    */
+/* (through the isocentre), u along lab y, v along lab z; source at          */
+/* (-src_dist, 0, 0).                                                        */
+
+/* Bin histories by (gantry angle, u, v) where their line crosses x = 0 and
+ * average the WEPL of each bin (an empty bin is 0). The bin is decided in FP32,
+ * everything else is FP64. proj: [n_angles][nv][nu]. Returns the number of
+ * histories binned. */
+int64_t or_fbp_bin(const or_hist *h, const or_fbp_params *p, double *proj)
+{
+    const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
+    double *cnt = (double *)calloc((size_t)nb, sizeof(double));
+    for (int64_t b = 0; b < nb; ++b) proj[b] = 0.0;
+    const float rdu = 1.0f / p->du_mm, rdv = 1.0f / p->dv_mm, rda = 1.0f / p->dangle_deg;
+    int64_t used = 0;
+    for (int64_t i = 0; i < h->n; ++i) {
+        const float xi = h->x_in[i], yi = h->y_in[i], zi = h->z_in[i];
+        const float xo = h->x_out[i], yo = h->y_out[i], zo = h->z_out[i];
+        const float a = h->angle_deg[i], w = h->wepl[i];
+        if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
+              isfinite(zo) && isfinite(a) && isfinite(w)))
+            continue;
+        const float ddx = xo - xi;
+        if (ddx == 0.0f) continue;
+        const float r = (0.0f - xi) / ddx;
+        const float u = yi + r * (yo - yi);
+        const float v = zi + r * (zo - zi);
+        const float fa = (a - p->angle0_deg) * rda;
+        const float fu = (u - p->u0_mm) * rdu;
+        const float fv = (v - p->v0_mm) * rdv;
+        if (!(fabsf(fa) < 1.0e9f)) continue;
+        if (!(fu >= 0.0f && fu < (float)p->nu && fv >= 0.0f && fv < (float)p->nv)) continue;
+        long k = lrintf(fa) % p->n_angles;
+        if (k < 0) k += p->n_angles;
+        const int64_t iu = (int64_t)floorf(fu), iv = (int64_t)floorf(fv);
+        const int64_t b = ((int64_t)k * p->nv + iv) * p->nu + iu;
+        proj[b] += (double)w;
+        cnt[b] += 1.0;
+        ++used;
+    }
+    for (int64_t b = 0; b < nb; ++b) proj[b] = cnt[b] > 0.0 ? proj[b] / cnt[b] : 0.0;
+    free(cnt);
+    return used;
+}
+
+/* Cosine pre-weight D / sqrt(D^2 + u^2 + v^2) at bin centres, then the
+ * Shepp-Logan filter along each detector row: q[i] = du * sum_j h[i-j] p[j],
+ * h[n] = -2 / (pi^2 du^2 (4 n^2 - 1)), the row taken as zero outside. In place. */
+void or_fbp_filter(const or_fbp_params *p, double *proj)
+{
+    const int64_t nu = p->nu, nv = p->nv;
+    const double D = p->src_dist_mm, du = p->du_mm, dv = p->dv_mm;
+    const double pi = 3.14159265358979323846;
+    double *row = (double *)malloc((size_t)nu * sizeof(double));
+    double *h = (double *)malloc((size_t)(2 * nu - 1) * sizeof(double));
+    for (int64_t n = -(nu - 1); n <= nu - 1; ++n)
+        h[n + nu - 1] = -2.0 / (pi * pi * du * du * (4.0 * (double)n * (double)n - 1.0));
+    for (int64_t k = 0; k < p->n_angles; ++k)
+        for (int64_t iv = 0; iv < nv; ++iv) {
+            double *pr = proj + (k * nv + iv) * nu;
+            const double vc = p->v0_mm + ((double)iv + 0.5) * dv;
+            for (int64_t iu = 0; iu < nu; ++iu) {
+                const double uc = p->u0_mm + ((double)iu + 0.5) * du;
+                row[iu] = pr[iu] * D / sqrt(D * D + uc * uc + vc * vc);
+            }
+            for (int64_t i = 0; i < nu; ++i) {
+                double acc = 0.0;
+                for (int64_t j = 0; j < nu; ++j) acc += h[i - j + nu - 1] * row[j];
+                pr[i] = du * acc;
+            }
+        }
+    free(h);
+    free(row);
+}
+
+/* FDK backprojection onto voxel centres: for each angle theta_k the voxel's
+ * lab position is R(theta_k) times its object position; with U = (D + x_L)/D
+ * the ray from the source meets the detector at (y_L/U, z/U); the filtered
+ * projection is sampled there bilinearly between bin centres (zero outside)
+ * and added with weight (dtheta/2) / U^2. image: [nz][ny][nx]. */
+void or_fbp_backproject(const or_grid *g, const or_fbp_params *p, const double *q, double *image)
+{
+    const double D = p->src_dist_mm, du = p->du_mm, dv = p->dv_mm;
+    const double pi = 3.14159265358979323846;
+    const double half_dth = 0.5 * (double)p->dangle_deg * pi / 180.0;
+    const int64_t nu = p->nu, nv = p->nv, nx = g->nx, ny = g->ny, nz = g->nz;
+    double *cs = (double *)malloc((size_t)p->n_angles * 2 * sizeof(double));
+    for (int64_t k = 0; k < p->n_angles; ++k) {
+        const double th = ((double)p->angle0_deg + (double)k * (double)p->dangle_deg) * pi / 180.0;
+        cs[2 * k] = cos(th);
+        cs[2 * k + 1] = sin(th);
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t kz = 0; kz < nz; ++kz)
+        for (int64_t jy = 0; jy < ny; ++jy)
+            for (int64_t ix = 0; ix < nx; ++ix) {
+                const double xo = (double)g->x0 + ((double)ix + 0.5) * (double)g->dx;
+                const double yo = (double)g->y0 + ((double)jy + 0.5) * (double)g->dy;
+                const double zo = (double)g->z0 + ((double)kz + 0.5) * (double)g->dz;
+                double f = 0.0;
+                for (int64_t k = 0; k < p->n_angles; ++k) {
+                    const double c = cs[2 * k], s = cs[2 * k + 1];
+                    const double xl = c * xo - s * yo;
+                    const double yl = s * xo + c * yo;
+                    const double U = (D + xl) / D;
+                    const double us = yl / U, vs = zo / U;
+                    const double fu = (us - p->u0_mm) / du - 0.5;
+                    const double fv = (vs - p->v0_mm) / dv - 0.5;
+                    const double iu0 = floor(fu), iv0 = floor(fv);
+                    const double a = fu - iu0, b = fv - iv0;
+                    double val = 0.0;
+                    for (int dj = 0; dj < 2; ++dj)
+                        for (int di = 0; di < 2; ++di) {
+                            const double iu = iu0 + di, iv = iv0 + dj;
+                            if (iu < 0.0 || iu >= (double)nu || iv < 0.0 || iv >= (double)nv) continue;
+                            const double wgt = (di ? a : 1.0 - a) * (dj ? b : 1.0 - b);
+                            val += wgt * q[(k * nv + (int64_t)iv) * nu + (int64_t)iu];
+                        }
+                    f += half_dth * val / (U * U);
+                }
+                image[(kz * ny + jy) * nx + ix] = f;
+            }
+    free(cs);
+}
+
+/* The whole FDK hull: bin, weight and filter, backproject, mask = [f >= thr].
+ * proj (optional) receives the filtered projections. Returns histories binned. */
+int64_t or_fbp(const or_hist *h, const or_grid *g, const or_fbp_params *p, double *proj,
+               double *image, uint8_t *mask)
+{
+    const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
+    double *q = proj ? proj : (double *)malloc((size_t)nb * sizeof(double));
+    const int64_t used = or_fbp_bin(h, p, q);
+    or_fbp_filter(p, q);
+    or_fbp_backproject(g, p, q, image);
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    if (mask)
+        for (int64_t v = 0; v < V; ++v) mask[v] = (uint8_t)(image[v] >= (double)p->threshold);
+    if (!proj) free(q);
+    return used;
+}
+
+/* Step 2 for histories [0, n): status per history (OR_OK or a skip reason)
+ * and the quantised endpoints as [n][3]. */
+void or_quantize_all(const or_hist *h, const or_grid *g, int32_t *status, int32_t *qin,
+                     int32_t *qout)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < h->n; ++i) status[i] = or_quantize(h, g, i, qin + 3 * i, qout + 3 * i);
+}
