@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of the hull path on one MI355X.
+
+One step = the whole hot path over one scan resident in HBM: the one-pass
+SC + MSC + SM call (classify, geometry, exact voxel walk, low/high counts, all
+three masks) and the FDK hull. The workload is the 200x200x32 scan with 1e7
+histories at 180 gantry angles (WEPL noise 3 mm, MSC count threshold 5, SM
+keeps M > 0.6 max M, FDK on 1 mm x 5 mm detector bins with Shepp-Logan).
+
+Prints one JSON line with throughput (histories/s), per-rule rates, step
+latency percentiles, the roofline of the dominant kernel (the walk) and a CPU
+baseline (the oracle timed on a bounded sample on this host).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs at 2.4 GHz, 64 int32 lanes per CU per clock; HBM3E 8 TB/s.
+PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+OPS_PER_VISIT = 6   # choose axis (2 compares), index, decision variable, address, count
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hull path is measured "
+              "on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    from paper_1402_1720_amd import hullmi as H
+
+    dev = torch.device("cuda:0")
+    spec = gen.config_spec(2)
+    geo = spec.fbp_geometry(du=1.0, dv=5.0)
+    t0 = time.time()
+    h = gen.generate(spec)
+    log(f"generated {spec.n_hist} histories in {time.time() - t0:.1f} s")
+    hist = H.Histories.from_numpy(h, dev)
+    grid = spec.grid
+    V = grid.voxels
+    n = spec.n_hist
+    params = H.make_params(wepl_low=1.0, wepl_high=5.0, msc_n_t=5, msc_mode=H.HULL_MSC_COUNT,
+                           sm_frac_num=3, sm_frac_den=5, sm_mode=H.HULL_SM_FRACTION)
+    fbp = H.make_fbp_params(geo)
+    N = torch.zeros(V, dtype=torch.int32, device=dev)
+    M = torch.zeros(V, dtype=torch.int32, device=dev)
+    sc, msc, sm, fmask = (torch.zeros(V, dtype=torch.uint8, device=dev) for _ in range(4))
+    image = torch.zeros(V, dtype=torch.float32, device=dev)
+    ws_all = H.workspace(H.HULL_OP_ALL, grid, n, dev)
+    ws_fbp = H.workspace(H.HULL_OP_FBP, grid, n, dev, fbp)
+    stats = torch.zeros(6, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        H.hull_all(hist, grid, params, N, M, sc, msc, sm, stats=stats, ws=ws_all, stream=stream)
+        H.hull_fbp(hist, grid, fbp, image, fmask, ws=ws_fbp, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps, events on the stream the library launches on
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        step()
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    per_step = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    ms_step = float(evs[0].elapsed_time(evs[-1]) / args.steps)
+    st = H.stats_dict(stats)
+    visits = st["n_visits_low"] + st["n_visits_high"]
+
+    def timed(fn, reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(3, args.steps)
+    # the walk kernel alone: with ACCUMULATE and no masks hull_all launches
+    # exactly one kernel (classify + geometry + walk + accumulate)
+    t_walk = timed(lambda: H.hull_all(hist, grid, params, N, M, flags=H.HULL_ACCUMULATE,
+                                      ws=ws_all, stream=stream), reps)
+    t_all = timed(lambda: H.hull_all(hist, grid, params, N, M, sc, msc, sm, ws=ws_all,
+                                     stream=stream), reps)
+    t_sc = timed(lambda: H.hull_sc(hist, grid, 1.0, N, sc, stream=stream), reps)
+    t_msc = timed(lambda: H.hull_msc(hist, grid, 1.0, 5, H.HULL_MSC_COUNT, H.HULL_NBR_INPLANE4, N,
+                                     msc, stream=stream), reps)
+    t_sm = timed(lambda: H.hull_sm(hist, grid, 5.0, 3, 5, H.HULL_SM_FRACTION, H.HULL_SCOPE_VOLUME,
+                                   H.HULL_NBR_INPLANE4, M, sm, ws=ws_all, stream=stream), reps)
+    t_fbp = timed(lambda: H.hull_fbp(hist, grid, fbp, image, fmask, ws=ws_fbp, stream=stream), reps)
+
+    # algorithmic work of one walk launch: 6 int lane-ops per voxel visit
+    achieved_tops = visits * OPS_PER_VISIT / (t_walk * 1e-3) / 1e12
+    # algorithmic HBM bytes of one walk launch: every WEPL, the other seven
+    # fields of the classified histories, N and M written back once
+    n_class = st["n_low"] + st["n_high"]
+    alg_bytes = 4 * n + 28 * n_class + 2 * 4 * V
+    hbm_gbs = alg_bytes / (t_walk * 1e-3) / 1e9
+
+    result = {
+        "metric": "proton histories/sec per hull algorithm (SC/MSC/SM) + %HBM roofline; p99 latency",
+        "value": n / (ms_step * 1e-3),
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32 walk / fp32 geometry+FDK",
+        "data": "synthetic",
+        "config": {"workload": "head phantom 200x200x32 (1x1x3 mm), 1e7 histories, 180 angles, "
+                               "sigma 3 mm; SC+MSC(count 5)+SM(0.6 max) one pass + FDK hull",
+                   "histories": n, "grid": list(grid.n), "angles": spec.n_angles},
+        "per_rule_histories_per_s": {
+            "sc": n / (t_sc * 1e-3), "msc": n / (t_msc * 1e-3), "sm": n / (t_sm * 1e-3),
+            "all_one_pass": n / (t_all * 1e-3), "fbp": n / (t_fbp * 1e-3)},
+        "latency_ms": {"p50": float(np.percentile(per_step, 50)),
+                       "p99": float(np.percentile(per_step, 99))},
+        "walk": {"ms": t_walk, "voxel_visits": visits, "visits_per_s": visits / (t_walk * 1e-3),
+                 "n_low": st["n_low"], "n_high": st["n_high"],
+                 "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
+        "roofline": {"bound": "alu", "kernel": "k_walk_histories", "achieved": achieved_tops,
+                     "peak": PEAK_INT_TOPS, "unit": "TOP/s", "frac": achieved_tops / PEAK_INT_TOPS,
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        S = min(args.cpu_sample, n)
+        sub = {k: v[:S] for k, v in h.items()}
+        G = oracle.grid_of(grid)
+        c0 = time.perf_counter()
+        rN, rM, _ = oracle.counts(sub, G)
+        oracle.sc(rN)
+        oracle.msc(rN, G, 5)
+        oracle.sm(rM, G, 3, 5)
+        c1 = time.perf_counter()
+        oracle.fbp(sub, G, oracle.fbp_params(geo))
+        c2 = time.perf_counter()
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # per-history work scales with the sample; the FDK backprojection is a
+        # fixed cost per scan, so the full-scan estimate adds it once
+        per_hist = (c1 - c0) / S
+        result["cpu_baseline"] = {
+            "value": n / (per_hist * n + (c2 - c1)), "unit": "histories/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {S} histories of the same scan: counts + SC/MSC/SM masks "
+                      f"({c1 - c0:.2f} s) and FDK ({c2 - c1:.2f} s); value = full-scan estimate "
+                      f"(per-history time x 1e7 + one FDK)"}
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * hullmi: proton-CT hull detection on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Schultze, Witt, Censor, Schulte and Schubert,
+ * "Performance of Hull-Detection Algorithms for Proton Computed Tomography
+ * Reconstruction" (arXiv:1402.1720): every proton history is a straight line
+ * through the image grid; low-WEPL lines feed silhouette/space carving (SC,
+ * Section 3.2, Algorithm 1) and modified SC (MSC, Section 3.3, Algorithm 2),
+ * high-WEPL lines feed space modelling (SM, Section 3.4, Algorithm 3), and a
+ * cone-beam FDK reconstruction thresholded at RSP 0.6 gives the FBP hull
+ * (Section 3.1).
+ *
+ * Conventions shared by every entry point
+ *   - Frames. Lab frame in mm: the beam runs along +x, z is the rotation axis.
+ *     The object turns by the gantry angle theta (degrees) in front of the
+ *     fixed beam (Section 2.2), so object coordinates are the lab coordinates
+ *     rotated by -theta about z. Grids live in the object frame.
+ *   - Geometry, decided bit-exactly: c, s = FP32 rounding of the FP64 cosine
+ *     and sine of (theta mod 360 computed exactly in FP64) * pi/180; each
+ *     endpoint becomes x_o = c*x + s*y, y_o = c*y - s*x, z_o = z (FP32, one
+ *     rounding per operation, no fused multiply-add), then voxel units
+ *     g = (x_o - x0) * (1.0f/dx), then q = rint(g * 1024) (round half to even).
+ *   - The voxel set A_i of a line (Sections 3.2 and 3.4, d0 read as 0 against
+ *     half-open voxel boxes, L_i read as the infinite line): voxel v belongs to
+ *     A_i when some point of the line through q_in and q_out lies in
+ *     [1024 v, 1024 (v+1)) on every axis. Integer arithmetic decides it.
+ *   - Classes (Section 3.2 eq. for I_L, Section 3.4 eq. for I_H): low when
+ *     WEPL < wepl_low, high when WEPL > wepl_high (FP32 compares).
+ *   - A history is skipped (counted in n_skipped, never an error) when its WEPL
+ *     is not finite, or when it belongs to a class being counted and another
+ *     field is not finite, an endpoint has |g| >= 2^16, or q_in == q_out.
+ *   - Volumes are [nz][ny][nx] with x fastest: v = i + nx*(j + ny*k).
+ *     Counts are int32, masks uint8 0/1.
+ *
+ * Memory and streams
+ *   - Histories, counts, masks, images, stats and workspace are DEVICE
+ *     pointers owned by the caller. Grid and parameter structs are host
+ *     pointers read before the call returns. Outputs must not alias inputs.
+ *   - Calls enqueue work on `stream` (a hipStream_t; NULL is the null stream)
+ *     and return without waiting. They allocate no device memory: the
+ *     workspace is passed in, sized by hull_workspace_bytes(). Calls on
+ *     different streams with disjoint outputs and workspaces may overlap.
+ *
+ * Errors
+ *   - Argument errors return HULL_EINVAL before anything is enqueued: a NULL
+ *     pointer that the call needs, n < 0 or n >= 2^31, a grid axis outside
+ *     [1, 2048] or with more than 2^31 - 1 voxels, a voxel size or origin that
+ *     is not finite or not positive, a non-finite threshold, n_t < 1,
+ *     frac_den <= 0, frac_num < 0, an unknown mode, scope or neighbourhood.
+ *   - A workspace smaller than hull_workspace_bytes() returns HULL_ENOMEM.
+ *   - A failed launch returns HULL_EDEVICE.
+ */
+#ifndef HULLMI_H
+#define HULLMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HULLMI_ABI_VERSION 1
+
+typedef enum hull_status {
+    HULL_OK = 0,
+    HULL_EINVAL = 1,
+    HULL_ENOMEM = 2,
+    HULL_EDEVICE = 3,
+    HULL_EBUSY = 4,
+    HULL_ENOTSUP = 5,
+    HULL_ETIMEDOUT = 6
+} hull_status;
+
+/* Voxel grid in the object frame (mm): (x0, y0, z0) is the lower corner of
+ * voxel (0, 0, 0); voxel (i, j, k) spans [x0 + i dx, x0 + (i+1) dx) etc. */
+typedef struct hullmi_grid {
+    int32_t nx, ny, nz;
+    float dx, dy, dz;
+    float x0, y0, z0;
+} hullmi_grid;
+
+/* Proton histories as eight FP32 device arrays of length n (structure of
+ * arrays): tracker entry and exit points (lab frame, mm), gantry angle
+ * (degrees) and water-equivalent path length (mm). */
+typedef struct hullmi_histories {
+    const float *x_in, *y_in, *z_in;
+    const float *x_out, *y_out, *z_out;
+    const float *angle_deg;
+    const float *wepl;
+    int64_t n;
+} hullmi_histories;
+
+/* Optional per-call counters (device memory). n_visits_* = sum of |A_i| over
+ * the counted low / high lines; n_missed_grid = counted lines with A_i empty. */
+typedef struct hullmi_stats {
+    int64_t n_low, n_high, n_skipped, n_missed_grid, n_visits_low, n_visits_high;
+} hullmi_stats;
+
+/* flags */
+#define HULL_ACCUMULATE 1u /* add to the counts (and stats) instead of overwriting */
+
+/* MSC rule. NEIGHBOR_DIFF is the paper's: keep v unless N(v) - N(w) >= n_t
+ * for some w in B(v) (Section 3.3, equation for H2 and Algorithm 2).
+ * COUNT keeps v when N(v) < n_t. */
+enum hull_msc_mode { HULL_MSC_COUNT = 0, HULL_MSC_NEIGHBOR_DIFF = 1 };
+/* SM threshold. MAX_SLOPE follows Algorithm 3: M_t = M at the last voxel (in
+ * linear order) whose slope max_{w in B(v)} M(v) - M(w) is largest; FRACTION
+ * sets M_t by frac_den * M > frac_num * max M. H3 = {M > M_t} (Section 3.4). */
+enum hull_sm_mode { HULL_SM_FRACTION = 0, HULL_SM_MAX_SLOPE = 1 };
+/* statistic of the SM threshold over the whole volume or per z-slice */
+enum hull_scope { HULL_SCOPE_VOLUME = 0, HULL_SCOPE_SLICE = 1 };
+/* B(v) = {w : d(v, w) <= 1} (Section 3.3) in voxel units: v and its face
+ * neighbours in the slice (INPLANE4) or in 3-D (SPATIAL6) */
+enum hull_nbr { HULL_NBR_INPLANE4 = 0, HULL_NBR_SPATIAL6 = 1 };
+
+/* operations for hull_workspace_bytes */
+enum hull_op {
+    HULL_OP_SC = 0,
+    HULL_OP_MSC = 1,
+    HULL_OP_SM = 2,
+    HULL_OP_ALL = 3,
+    HULL_OP_FBP = 4,
+    HULL_OP_COUNT_LINES = 5
+};
+
+/* All parameters of the one-pass call. The paper's values: wepl_low 1.0 mm
+ * (Sections 3.2, 3.3), wepl_high 5.0 mm (Section 3.4), msc_n_t 50 with
+ * NEIGHBOR_DIFF (Section 3.3). */
+typedef struct hullmi_params {
+    float wepl_low, wepl_high;
+    int32_t msc_n_t, msc_mode;
+    int32_t sm_frac_num, sm_frac_den, sm_mode, sm_scope;
+    int32_t nbr;
+} hullmi_params;
+
+/* FDK geometry (Section 3.1): virtual detector on the lab plane x = 0, u along
+ * lab y, v along lab z, nu x nv bins of du x dv mm starting at (u0, v0); the
+ * point source sits at (-src_dist, 0, 0); n_angles gantry angle bins of
+ * dangle degrees from angle0 covering the full turn; nu <= 2048 and
+ * nu * nv * n_angles < 2^31. filter 0 = Shepp-Logan.
+ * threshold: RSP at or above it belongs to the hull (0.6 in the paper). */
+typedef struct hullmi_fbp_params {
+    float src_dist_mm, du_mm, dv_mm, u0_mm, v0_mm;
+    int32_t nu, nv, n_angles;
+    float angle0_deg, dangle_deg;
+    int32_t filter;
+    float threshold;
+} hullmi_fbp_params;
+
+/* HULLMI_ABI_VERSION of the loaded library. */
+int hull_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *hull_strerror(int status);
+
+/* Device workspace (bytes, 256-byte aligned start expected) that `op` needs
+ * for a grid and n histories (fbp may be NULL unless op is HULL_OP_FBP).
+ * Returns 0 when nothing is needed, or (size_t)-1 on invalid arguments. */
+size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n,
+                            const hullmi_fbp_params *fbp);
+
+/* SC (Section 3.2, Algorithm 1): N[v] = number of low lines whose A_i holds v;
+ * mask[v] = (N[v] == 0). N (required) and mask (may be NULL) are device
+ * arrays of nx*ny*nz elements. stats may be NULL. */
+int hull_sc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low,
+            int32_t *N, uint8_t *mask, uint32_t flags, hullmi_stats *stats,
+            void *ws, size_t ws_bytes, void *stream);
+
+/* MSC (Section 3.3, Algorithm 2): the same N, then the MSC mask by `mode`
+ * (hull_msc_mode) with threshold n_t and neighbourhood `nbr` (hull_nbr). */
+int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low,
+             int32_t n_t, int mode, int nbr, int32_t *N, uint8_t *mask, uint32_t flags,
+             hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* SM (Section 3.4, Algorithm 3): M[v] = number of high lines whose A_i holds
+ * v; mask by `mode` (hull_sm_mode), `scope` (hull_scope) and `nbr`. FRACTION
+ * uses frac_num / frac_den (for example 3 / 5 keeps M > 0.6 max M). */
+int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_high,
+            int32_t frac_num, int32_t frac_den, int mode, int scope, int nbr, int32_t *M,
+            uint8_t *mask, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
+            void *stream);
+
+/* One pass over the histories for all three rules: low lines count into N,
+ * high lines into M, then the SC, MSC and SM masks (each may be NULL). */
+int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *params,
+             int32_t *N, int32_t *M, uint8_t *sc_mask, uint8_t *msc_mask, uint8_t *sm_mask,
+             uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* FDK hull (Section 3.1). Every history with finite fields, |WEPL| < 2^16 mm
+ * and x_out != x_in is binned by (gantry angle, u, v) where its line crosses
+ * x = 0 (decided in FP32: r = (0 - x_in)/(x_out - x_in), u = y_in + r*(y_out -
+ * y_in), v likewise, k = rint((theta - angle0) * (1/dangle)) mod n_angles,
+ * iu = floor((u - u0) * (1/du)), iv likewise); bins average their WEPL
+ * (empty bins are 0), are weighted by D / sqrt(D^2 + u^2 + v^2), filtered
+ * along u with the Shepp-Logan kernel -2 / (pi^2 du^2 (4 n^2 - 1)) times du,
+ * and backprojected onto voxel centres with weight (dtheta/2) / U^2, U =
+ * (D + x_L)/D, sampling bilinearly (zero off the detector). image (FP32,
+ * required) gets the RSP estimate, mask (may be NULL) = image >= threshold. */
+int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+             float *image, uint8_t *mask, void *ws, size_t ws_bytes, void *stream);
+
+/* The accumulate step alone, for lines already in quantised object-frame form
+ * (for example one line per bin): q_in and q_out are device arrays [n][3] of
+ * int32 in 1/1024-voxel units; counts[v] gets the number of lines whose A_i
+ * holds v (added to when flags has HULL_ACCUMULATE). Lines with q_in == q_out
+ * or a coordinate of magnitude 2^26 or more are skipped. */
+int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n,
+                     const hullmi_grid *grid, int32_t *counts, uint32_t flags,
+                     hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* The geometry step alone: per history status (0 ok, 1 non-finite field,
+ * 2 endpoint out of range, 3 degenerate) and the quantised endpoints [n][3]
+ * (int32, 1/1024 voxel; left unwritten for status 1 and 2). */
+int hull_quantize(const hullmi_histories *hist, const hullmi_grid *grid, int32_t *status,
+                  int32_t *q_in, int32_t *q_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HULLMI_H */

@@ -254,15 +254,21 @@ int64_t or_line_cells(const int32_t qin[3], const int32_t qout[3], const or_grid
     return or_cells(P0, D, g, all, out, cap, NULL);
 }
 
-/* counts[v] += |{lines i : v in A_i}| for n quantised lines given as [n][3]. */
+/* counts[v] += |{lines i : v in A_i}| for n quantised lines given as [n][3].
+ * Lines with q_in == q_out or a coordinate of magnitude 2^26 or more are
+ * skipped (the same bound that endpoints within 2^16 voxels satisfy). */
 void or_count_lines(const int32_t *qin, const int32_t *qout, int64_t n, const or_grid *g,
                     int32_t *counts)
 {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; ++i) {
         const int64_t P0[3] = {qin[3 * i], qin[3 * i + 1], qin[3 * i + 2]};
-        const int64_t D[3] = {(int64_t)qout[3 * i] - P0[0], (int64_t)qout[3 * i + 1] - P0[1],
-                              (int64_t)qout[3 * i + 2] - P0[2]};
+        const int64_t P1[3] = {qout[3 * i], qout[3 * i + 1], qout[3 * i + 2]};
+        int ok = 1;
+        for (int a = 0; a < 3; ++a)
+            ok &= llabs(P0[a]) < (1LL << 26) && llabs(P1[a]) < (1LL << 26);
+        if (!ok) continue;
+        const int64_t D[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
         if (D[0] == 0 && D[1] == 0 && D[2] == 0) continue;
         or_cells(P0, D, g, 0, NULL, 0, counts);
     }
@@ -271,20 +277,17 @@ void or_count_lines(const int32_t *qin, const int32_t *qout, int64_t n, const or
 /* Steps 1-4 over histories [0, n): N counts low histories (WEPL < e_low),
  * M counts high ones (WEPL > e_high). Either output may be NULL, which also
  * switches its class off. Counts are added to what N and M hold.
- * A history with a non-finite field is skipped; so is a history of an active
- * class whose endpoints leave |g| < 2^16 or coincide after rounding. */
+ * Skipped (and counted in n_skipped): a history whose WEPL is not finite, and
+ * a history of an active class with another field not finite, an endpoint
+ * with |g| >= 2^16, or endpoints that coincide after rounding. */
 void or_counts(const or_hist *h, const or_grid *g, float e_low, float e_high,
                int32_t *N, int32_t *M, or_stats *st)
 {
     int64_t s_low = 0, s_high = 0, s_skip = 0, s_miss = 0, s_vl = 0, s_vh = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : s_low, s_high, s_skip, s_miss, s_vl, s_vh)
     for (int64_t i = 0; i < h->n; ++i) {
-        const float f[8] = {h->x_in[i], h->y_in[i], h->z_in[i], h->x_out[i],
-                            h->y_out[i], h->z_out[i], h->angle_deg[i], h->wepl[i]};
-        int finite = 1;
-        for (int k = 0; k < 8; ++k) finite &= isfinite(f[k]) != 0;
-        if (!finite) { ++s_skip; continue; }
         const float w = h->wepl[i];
+        if (!isfinite(w)) { ++s_skip; continue; }
         const int low = N != NULL && w < e_low;
         const int high = M != NULL && w > e_high;
         if (!low && !high) continue;
@@ -409,8 +412,9 @@ int or_sm(const int32_t *M, const or_grid *g, int32_t num, int32_t den, int mode
 
 /* Bin histories by (gantry angle, u, v) where their line crosses x = 0 and
  * average the WEPL of each bin (an empty bin is 0). The bin is decided in FP32,
- * everything else is FP64. proj: [n_angles][nv][nu]. Returns the number of
- * histories binned. */
+ * everything else is FP64. Histories with a non-finite field, |WEPL| >= 2^16 mm
+ * (far beyond any proton range) or x_out == x_in are not binned.
+ * proj: [n_angles][nv][nu]. Returns the number of histories binned. */
 int64_t or_fbp_bin(const or_hist *h, const or_fbp_params *p, double *proj)
 {
     const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
@@ -425,6 +429,7 @@ int64_t or_fbp_bin(const or_hist *h, const or_fbp_params *p, double *proj)
         if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
               isfinite(zo) && isfinite(a) && isfinite(w)))
             continue;
+        if (!(fabsf(w) < 65536.0f)) continue;
         const float ddx = xo - xi;
         if (ddx == 0.0f) continue;
         const float r = (0.0f - xi) / ddx;

@@ -1,0 +1,345 @@
+// Host side of the C ABI declared in hullmi.h: argument checks, workspace
+// layout and kernel launches. Everything here runs on the calling thread and
+// only enqueues work on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "hull_device.h"
+#include "hull_kernels.h"
+#include "hullmi.h"
+
+namespace hullmi {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxAxis = 2048;
+constexpr int kMaxNu = 2048;     // detector bins per row (the filter keeps a row in LDS)
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+bool grid_ok(const hullmi_grid *g)
+{
+    if (!g) return false;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
+    if (g->nx > kMaxAxis || g->ny > kMaxAxis || g->nz > kMaxAxis) return false;
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    if (V > INT32_MAX) return false;
+    if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz)) return false;
+    if (!std::isfinite(g->x0) || !std::isfinite(g->y0) || !std::isfinite(g->z0)) return false;
+    // voxel units must stay finite: 1/dx rounded in FP32 must not overflow
+    if (!std::isfinite(1.0f / g->dx) || !std::isfinite(1.0f / g->dy) || !std::isfinite(1.0f / g->dz))
+        return false;
+    return true;
+}
+
+inline int64_t voxels(const hullmi_grid *g) { return (int64_t)g->nx * g->ny * g->nz; }
+
+bool hist_ok(const hullmi_histories *h)
+{
+    if (!h) return false;
+    if (h->n < 0 || h->n > INT32_MAX) return false;
+    if (h->n == 0) return true;
+    return h->x_in && h->y_in && h->z_in && h->x_out && h->y_out && h->z_out && h->angle_deg &&
+           h->wepl;
+}
+
+bool fbp_ok(const hullmi_fbp_params *p)
+{
+    if (!p) return false;
+    if (!finite_pos(p->src_dist_mm) || !finite_pos(p->du_mm) || !finite_pos(p->dv_mm) ||
+        !finite_pos(p->dangle_deg))
+        return false;
+    if (!std::isfinite(p->u0_mm) || !std::isfinite(p->v0_mm) || !std::isfinite(p->angle0_deg) ||
+        !std::isfinite(p->threshold))
+        return false;
+    if (p->nu < 1 || p->nv < 1 || p->n_angles < 1 || p->nu > kMaxNu) return false;
+    if ((int64_t)p->nu * p->nv * p->n_angles > INT32_MAX) return false;
+    if (p->filter != 0) return false;
+    return true;
+}
+
+DevGrid dev_grid(const hullmi_grid *g)
+{
+    DevGrid d;
+    d.nx = g->nx; d.ny = g->ny; d.nz = g->nz;
+    d.rdx = 1.0f / g->dx; d.rdy = 1.0f / g->dy; d.rdz = 1.0f / g->dz;
+    d.x0 = g->x0; d.y0 = g->y0; d.z0 = g->z0;
+    return d;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int launch_status()
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HULL_OK : HULL_EDEVICE;
+}
+
+void fill_u32(void *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (!p || n <= 0) return;
+    const unsigned b = (unsigned)std::min<int64_t>(blocks_for(n), 4096);
+    k_fill_u32<<<b, kBlock, 0, s>>>(reinterpret_cast<uint32_t *>(p), v, n);
+}
+
+void fill_u64(void *p, unsigned long long v, int64_t n, hipStream_t s)
+{
+    if (!p || n <= 0) return;
+    const unsigned b = (unsigned)std::min<int64_t>(blocks_for(n), 4096);
+    k_fill_u64<<<b, kBlock, 0, s>>>(reinterpret_cast<unsigned long long *>(p), v, n);
+}
+
+// Workspace of the SM rules: one 64-bit slot per z-slice (covers both scopes).
+size_t sm_ws_bytes(const hullmi_grid *g) { return align_up((size_t)g->nz * 8); }
+
+struct FbpWs {
+    unsigned long long *sum;
+    unsigned *cnt;
+    float *q;
+    float2 *cs;
+    size_t bytes;
+};
+
+FbpWs fbp_ws_layout(const hullmi_fbp_params *p, void *base)
+{
+    const size_t nb = (size_t)p->nu * p->nv * p->n_angles;
+    FbpWs w;
+    char *b = reinterpret_cast<char *>(base);
+    size_t off = 0;
+    w.sum = reinterpret_cast<unsigned long long *>(b + off); off += align_up(nb * 8);
+    w.cnt = reinterpret_cast<unsigned *>(b + off);           off += align_up(nb * 4);
+    w.q = reinterpret_cast<float *>(b + off);                off += align_up(nb * 4);
+    w.cs = reinterpret_cast<float2 *>(b + off);              off += align_up((size_t)p->n_angles * 8);
+    w.bytes = off;
+    return w;
+}
+
+// Zero (unless accumulating) and count: the shared core of every hull call.
+int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, float e_high, int32_t *N,
+               int32_t *M, uint32_t flags, hullmi_stats *stats, hipStream_t s)
+{
+    const int64_t V = voxels(g);
+    if (!(flags & HULL_ACCUMULATE)) {
+        fill_u32(N, 0u, N ? V : 0, s);
+        fill_u32(M, 0u, M ? V : 0, s);
+        fill_u64(stats, 0ull, stats ? 6 : 0, s);
+    }
+    if (h->n > 0) {
+        k_walk_histories<<<blocks_for(h->n), kBlock, 0, s>>>(*h, dev_grid(g), e_low, e_high, N, M,
+                                                            stats);
+    }
+    return launch_status();
+}
+
+int run_msc_mask(const hullmi_grid *g, const int32_t *N, uint8_t *mask, int n_t, int mode, int nbr,
+                 hipStream_t s)
+{
+    if (!mask) return HULL_OK;
+    const int64_t V = voxels(g);
+    k_msc_mask<<<blocks_for(V), kBlock, 0, s>>>(N, mask, g->nx, g->ny, g->nz, n_t, mode, nbr);
+    return launch_status();
+}
+
+int run_sm_mask(const hullmi_grid *g, const int32_t *M, uint8_t *mask, int num, int den, int mode,
+                int scope, int nbr, void *ws, hipStream_t s)
+{
+    if (!mask) return HULL_OK;
+    const int64_t V = voxels(g);
+    const int64_t seg_len = scope == HULL_SCOPE_SLICE ? (int64_t)g->nx * g->ny : V;
+    const int64_t nseg = V / seg_len;
+    auto *seg = reinterpret_cast<unsigned long long *>(ws);
+    fill_u64(seg, 0ull, nseg, s);
+    if (mode == HULL_SM_FRACTION)
+        k_seg_max<<<blocks_for(V), kBlock, 0, s>>>(M, seg, V, seg_len);
+    else
+        k_seg_slope_argmax<<<blocks_for(V), kBlock, 0, s>>>(M, seg, g->nx, g->ny, g->nz, nbr, seg_len);
+    k_sm_mask<<<blocks_for(V), kBlock, 0, s>>>(M, mask, V, seg_len, mode, num, den, seg);
+    return launch_status();
+}
+
+bool msc_args_ok(int n_t, int mode, int nbr)
+{
+    return n_t >= 1 && (mode == HULL_MSC_COUNT || mode == HULL_MSC_NEIGHBOR_DIFF) &&
+           (nbr == HULL_NBR_INPLANE4 || nbr == HULL_NBR_SPATIAL6);
+}
+
+bool sm_args_ok(int num, int den, int mode, int scope, int nbr)
+{
+    return den > 0 && num >= 0 && (mode == HULL_SM_FRACTION || mode == HULL_SM_MAX_SLOPE) &&
+           (scope == HULL_SCOPE_VOLUME || scope == HULL_SCOPE_SLICE) &&
+           (nbr == HULL_NBR_INPLANE4 || nbr == HULL_NBR_SPATIAL6);
+}
+
+}  // namespace
+}  // namespace hullmi
+
+using namespace hullmi;
+
+extern "C" {
+
+int hull_abi_version(void) { return HULLMI_ABI_VERSION; }
+
+const char *hull_strerror(int status)
+{
+    switch (status) {
+    case HULL_OK: return "ok";
+    case HULL_EINVAL: return "invalid argument";
+    case HULL_ENOMEM: return "workspace too small";
+    case HULL_EDEVICE: return "device launch failed";
+    case HULL_EBUSY: return "busy";
+    case HULL_ENOTSUP: return "not supported";
+    case HULL_ETIMEDOUT: return "timed out";
+    default: return "unknown status";
+    }
+}
+
+size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_params *fbp)
+{
+    if (n < 0) return (size_t)-1;
+    switch (op) {
+    case HULL_OP_SC:
+    case HULL_OP_MSC:
+    case HULL_OP_COUNT_LINES:
+        if (!grid_ok(grid)) return (size_t)-1;
+        return 0;
+    case HULL_OP_SM:
+    case HULL_OP_ALL:
+        if (!grid_ok(grid)) return (size_t)-1;
+        return sm_ws_bytes(grid);
+    case HULL_OP_FBP:
+        if (!grid_ok(grid) || !fbp_ok(fbp)) return (size_t)-1;
+        return fbp_ws_layout(fbp, nullptr).bytes;
+    default:
+        return (size_t)-1;
+    }
+}
+
+int hull_sc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t *N,
+            uint8_t *mask, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
+            void *stream)
+{
+    (void)ws; (void)ws_bytes;
+    if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low)) return HULL_EINVAL;
+    hipStream_t s = as_stream(stream);
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, s);
+    if (rc != HULL_OK) return rc;
+    if (mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, mask, voxels(grid));
+    return launch_status();
+}
+
+int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t n_t,
+             int mode, int nbr, int32_t *N, uint8_t *mask, uint32_t flags, hullmi_stats *stats,
+             void *ws, size_t ws_bytes, void *stream)
+{
+    (void)ws; (void)ws_bytes;
+    if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low) ||
+        !msc_args_ok(n_t, mode, nbr))
+        return HULL_EINVAL;
+    hipStream_t s = as_stream(stream);
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, s);
+    if (rc != HULL_OK) return rc;
+    return run_msc_mask(grid, N, mask, n_t, mode, nbr, s);
+}
+
+int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_high, int32_t frac_num,
+            int32_t frac_den, int mode, int scope, int nbr, int32_t *M, uint8_t *mask,
+            uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !M || !std::isfinite(wepl_high) ||
+        !sm_args_ok(frac_num, frac_den, mode, scope, nbr))
+        return HULL_EINVAL;
+    if (mask && (!ws || ws_bytes < sm_ws_bytes(grid))) return HULL_ENOMEM;
+    hipStream_t s = as_stream(stream);
+    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, s);
+    if (rc != HULL_OK) return rc;
+    return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr, ws, s);
+}
+
+int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
+             int32_t *N, int32_t *M, uint8_t *sc_mask, uint8_t *msc_mask, uint8_t *sm_mask,
+             uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !p || !N || !M) return HULL_EINVAL;
+    if (!std::isfinite(p->wepl_low) || !std::isfinite(p->wepl_high)) return HULL_EINVAL;
+    if (msc_mask && !msc_args_ok(p->msc_n_t, p->msc_mode, p->nbr)) return HULL_EINVAL;
+    if (sm_mask && !sm_args_ok(p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr))
+        return HULL_EINVAL;
+    if (sm_mask && (!ws || ws_bytes < sm_ws_bytes(grid))) return HULL_ENOMEM;
+    hipStream_t s = as_stream(stream);
+    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, s);
+    if (rc != HULL_OK) return rc;
+    if (sc_mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, sc_mask, voxels(grid));
+    rc = launch_status();
+    if (rc == HULL_OK) rc = run_msc_mask(grid, N, msc_mask, p->msc_n_t, p->msc_mode, p->nbr, s);
+    if (rc == HULL_OK)
+        rc = run_sm_mask(grid, M, sm_mask, p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope,
+                         p->nbr, ws, s);
+    return rc;
+}
+
+int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+             float *image, uint8_t *mask, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image) return HULL_EINVAL;
+    const size_t need = fbp_ws_layout(fbp, nullptr).bytes;
+    if (!ws || ws_bytes < need) return HULL_ENOMEM;
+    hipStream_t s = as_stream(stream);
+    FbpWs w = fbp_ws_layout(fbp, ws);
+    FbpDev p;
+    p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
+    p.u0 = fbp->u0_mm; p.v0 = fbp->v0_mm;
+    p.rdu = 1.0f / fbp->du_mm; p.rdv = 1.0f / fbp->dv_mm; p.rda = 1.0f / fbp->dangle_deg;
+    p.angle0 = fbp->angle0_deg; p.dangle = fbp->dangle_deg; p.threshold = fbp->threshold;
+    p.half_dth = (float)(0.5 * (double)fbp->dangle_deg * 3.14159265358979323846 / 180.0);
+    p.nu = fbp->nu; p.nv = fbp->nv; p.n_angles = fbp->n_angles;
+    const int64_t nb = (int64_t)p.nu * p.nv * p.n_angles;
+    fill_u64(w.sum, 0ull, nb, s);
+    fill_u32(w.cnt, 0u, nb, s);
+    if (hist->n > 0) k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
+    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(double);
+    k_fbp_filter<<<(unsigned)(p.n_angles * p.nv), kBlock, lds, s>>>(w.sum, w.cnt, w.q, p);
+    k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
+    FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
+                  grid->x0, grid->y0, grid->z0};
+    k_fbp_backproject<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(w.q, w.cs, p, gd, image, mask);
+    return launch_status();
+}
+
+int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n, const hullmi_grid *grid,
+                     int32_t *counts, uint32_t flags, hullmi_stats *stats, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    (void)ws; (void)ws_bytes;
+    if (!grid_ok(grid) || !counts || n < 0 || n > INT32_MAX) return HULL_EINVAL;
+    if (n > 0 && (!q_in || !q_out)) return HULL_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (!(flags & HULL_ACCUMULATE)) {
+        fill_u32(counts, 0u, voxels(grid), s);
+        fill_u64(stats, 0ull, stats ? 6 : 0, s);
+    }
+    if (n > 0)
+        k_walk_lines<<<blocks_for(n), kBlock, 0, s>>>(q_in, q_out, n, grid->nx, grid->ny, grid->nz,
+                                                     counts, stats);
+    return launch_status();
+}
+
+int hull_quantize(const hullmi_histories *hist, const hullmi_grid *grid, int32_t *status,
+                  int32_t *q_in, int32_t *q_out, void *stream)
+{
+    if (!hist_ok(hist) || !grid_ok(grid)) return HULL_EINVAL;
+    if (hist->n > 0 && (!status || !q_in || !q_out)) return HULL_EINVAL;
+    if (hist->n > 0)
+        k_quantize<<<blocks_for(hist->n), kBlock, 0, as_stream(stream)>>>(*hist, dev_grid(grid),
+                                                                         status, q_in, q_out);
+    return launch_status();
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Device-side building blocks of the hull path for gfx950: the FP32 geometry
+// that turns a history into a quantised object-frame line, and the exact
+// integer walk that enumerates the voxel set A_i of that line (Sections 3.2
+// and 3.4 of the paper; A_i read as the half-open voxel boxes that the
+// infinite line meets).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hullmi {
+
+constexpr int kQ = 1024;            // endpoints in units of 1/1024 voxel
+constexpr float kGMax = 65536.0f;   // |g| < 2^16 voxels
+
+enum : int { kGeoOk = 0, kGeoNonFinite = 1, kGeoRange = 2, kGeoDegenerate = 3 };
+
+struct DevGrid {
+    int nx, ny, nz;
+    float rdx, rdy, rdz;   // 1.0f / voxel size, rounded once on the host
+    float x0, y0, z0;
+};
+
+// cos/sin of an angle in degrees: remainder modulo 360 (exact in FP64), FP64
+// cos/sin, rounded to FP32.
+__device__ __forceinline__ void deg_cos_sin(float a, float &c, float &s)
+{
+    const double th = (double)a;
+    const double r = th - 360.0 * floor(th / 360.0);
+    const double rad = r * 0.017453292519943295;
+    c = (float)cos(rad);
+    s = (float)sin(rad);
+}
+
+// Object frame (lab rotated by -theta about z), voxel units, 1/1024 rounding.
+__device__ __forceinline__ int quantize_point(float c, float s, float x, float y, float z,
+                                              const DevGrid &g, int &qx, int &qy, int &qz)
+{
+    const float xo = c * x + s * y;
+    const float yo = c * y - s * x;
+    const float gx = (xo - g.x0) * g.rdx;
+    const float gy = (yo - g.y0) * g.rdy;
+    const float gz = (z - g.z0) * g.rdz;
+    if (!(fabsf(gx) < kGMax && fabsf(gy) < kGMax && fabsf(gz) < kGMax)) return kGeoRange;
+    qx = (int)rintf(gx * (float)kQ);
+    qy = (int)rintf(gy * (float)kQ);
+    qz = (int)rintf(gz * (float)kQ);
+    return kGeoOk;
+}
+
+// floor(a / b) for b > 0: an FP64 estimate corrected with exact products
+// (|a| < 2^56, b < 2^38, so the estimate is off by at most one).
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b)
+{
+    int64_t q = (int64_t)floor((double)a / (double)b);
+    if (q * b > a) --q;
+    if ((q + 1) * b <= a) ++q;
+    return q;
+}
+
+__device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
+
+__device__ __forceinline__ int64_t sel3(int w, int64_t a, int64_t b, int64_t c)
+{
+    return w == 0 ? a : (w == 1 ? b : c);
+}
+
+// Walk state after set-up: the first voxel of A_i and, per axis, the next
+// crossing written as pairwise decision variables.
+//
+// Parameterise the line as P(t) = P0 + t D. The index on a moving axis a
+// changes at plane crossings; with the half-open reading an increasing axis
+// takes its new index at the crossing itself and a decreasing axis just after
+// it. Order crossings by the key (t, sigma) with sigma = 0 for increasing and
+// 1 for decreasing axes; crossings with equal keys happen together. With
+// e_a / A_a the t of axis a's next crossing (A_a = |D_a|), the key order of
+// axes a and b is the sign of d_ab = 2 (e_a A_b - e_b A_a) + (sigma_a -
+// sigma_b): exact, integer, and updated by +-2048 A when an axis steps.
+// A fixed axis gets e = 1, A = 0, sigma = 0, which makes it never step.
+struct WalkInit {
+    int cx, cy, cz;          // first voxel
+    int64_t dxy, dxz, dyz;   // decision variables
+    int64_t Ax, Ay, Az;      // |D|
+    int sx, sy, sz;          // +-1 per axis
+};
+
+// Returns false when the line misses the grid.
+__device__ __forceinline__ bool walk_init(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                          int nx, int ny, int nz, WalkInit &w)
+{
+    const int64_t Px = qix, Py = qiy, Pz = qiz;
+    const int64_t Dx = (int64_t)qox - qix, Dy = (int64_t)qoy - qiy, Dz = (int64_t)qoz - qiz;
+    const int64_t Lx = (int64_t)kQ * nx, Ly = (int64_t)kQ * ny, Lz = (int64_t)kQ * nz;
+    // a fixed axis must already lie inside the grid
+    if (Dx == 0 && (Px < 0 || Px >= Lx)) return false;
+    if (Dy == 0 && (Py < 0 || Py >= Ly)) return false;
+    if (Dz == 0 && (Pz < 0 || Pz >= Lz)) return false;
+    const int64_t Ax = Dx < 0 ? -Dx : Dx, Ay = Dy < 0 ? -Dy : Dy, Az = Dz < 0 ? -Dz : Dz;
+    // entry key of each moving axis: t = en / A, sigma = (D < 0)
+    const int64_t enx = Dx > 0 ? -Px : Px - Lx;
+    const int64_t eny = Dy > 0 ? -Py : Py - Ly;
+    const int64_t enz = Dz > 0 ? -Pz : Pz - Lz;
+    const int gx = Dx < 0, gy = Dy < 0, gz = Dz < 0;
+    // the latest entry key decides where the line enters the grid
+    int wa = -1;
+    int64_t ew = 0, aw = 1;
+    int gw = 0;
+    if (Ax) { wa = 0; ew = enx; aw = Ax; gw = gx; }
+    if (Ay) {
+        const int64_t l = eny * aw, r = ew * Ay;
+        if (wa < 0 || l > r || (l == r && gy > gw)) { wa = 1; ew = eny; aw = Ay; gw = gy; }
+    }
+    if (Az) {
+        const int64_t l = enz * aw, r = ew * Az;
+        if (wa < 0 || l > r || (l == r && gz > gw)) { wa = 2; ew = enz; aw = Az; gw = gz; }
+    }
+    const int64_t den = (int64_t)kQ * aw;
+    // voxel index of each axis at the entry key
+    int64_t c[3];
+    const int64_t P[3] = {Px, Py, Pz}, D[3] = {Dx, Dy, Dz};
+    const int n[3] = {nx, ny, nz};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (b == wa) {
+            c[b] = D[b] > 0 ? 0 : n[b] - 1;
+        } else if (D[b] == 0) {
+            c[b] = P[b] >> 10;
+        } else {
+            const int64_t num = P[b] * aw + D[b] * ew;
+            c[b] = (gw && D[b] < 0) ? ceil_div(num, den) - 1 : floor_div(num, den);
+        }
+        if (c[b] < 0 || c[b] >= n[b]) return false;
+    }
+    // next crossing per axis
+    const int64_t ex = Dx > 0 ? (int64_t)kQ * (c[0] + 1) - Px : (Dx < 0 ? Px - (int64_t)kQ * c[0] : 1);
+    const int64_t ey = Dy > 0 ? (int64_t)kQ * (c[1] + 1) - Py : (Dy < 0 ? Py - (int64_t)kQ * c[1] : 1);
+    const int64_t ez = Dz > 0 ? (int64_t)kQ * (c[2] + 1) - Pz : (Dz < 0 ? Pz - (int64_t)kQ * c[2] : 1);
+    w.dxy = 2 * (ex * Ay - ey * Ax) + (gx - gy);
+    w.dxz = 2 * (ex * Az - ez * Ax) + (gx - gz);
+    w.dyz = 2 * (ey * Az - ez * Ay) + (gy - gz);
+    w.Ax = Ax; w.Ay = Ay; w.Az = Az;
+    w.cx = (int)c[0]; w.cy = (int)c[1]; w.cz = (int)c[2];
+    w.sx = Dx > 0 ? 1 : -1; w.sy = Dy > 0 ? 1 : -1; w.sz = Dz > 0 ? 1 : -1;
+    return true;
+}
+
+// Enumerates A_i from the initial voxel, calling acc(linear_index) once per
+// voxel, and returns |A_i|. T holds the decision variables: int32 is exact
+// when every |D| < 2^19 (then |d| <= 4096 max A + 1 < 2^31 at every step),
+// int64 always.
+template <typename T, class Acc>
+__device__ __forceinline__ int walk_run(const WalkInit &w, int nx, int ny, int nz, Acc &acc)
+{
+    T dxy = (T)w.dxy, dxz = (T)w.dxz, dyz = (T)w.dyz;
+    const T Kx = (T)(2048 * w.Ax), Ky = (T)(2048 * w.Ay), Kz = (T)(2048 * w.Az);
+    int cx = w.cx, cy = w.cy, cz = w.cz;
+    const int ox = w.sx, oy = w.sy * nx, oz = w.sz * nx * ny;
+    int off = cx + nx * (cy + ny * cz);
+    const int maxit = nx + ny + nz;
+    int cnt = 0;
+    for (int it = 0; it < maxit; ++it) {
+        acc(off);
+        ++cnt;
+        const bool bx = (dxy <= 0) & (dxz <= 0);
+        const bool by = (dxy >= 0) & (dyz <= 0);
+        const bool bz = (dxz >= 0) & (dyz >= 0);
+        dxy += (bx ? Ky : (T)0) - (by ? Kx : (T)0);
+        dxz += (bx ? Kz : (T)0) - (bz ? Kx : (T)0);
+        dyz += (by ? Kz : (T)0) - (bz ? Ky : (T)0);
+        cx += bx ? w.sx : 0;
+        cy += by ? w.sy : 0;
+        cz += bz ? w.sz : 0;
+        off += (bx ? ox : 0) + (by ? oy : 0) + (bz ? oz : 0);
+        if (((unsigned)cx >= (unsigned)nx) | ((unsigned)cy >= (unsigned)ny) |
+            ((unsigned)cz >= (unsigned)nz))
+            break;
+    }
+    return cnt;
+}
+
+template <class Acc>
+__device__ __forceinline__ int walk_line(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                         int nx, int ny, int nz, Acc &acc)
+{
+    WalkInit w;
+    if (!walk_init(qix, qiy, qiz, qox, qoy, qoz, nx, ny, nz, w)) return 0;
+    const int64_t amax = max(w.Ax, max(w.Ay, w.Az));
+    if (amax < (int64_t(1) << 19)) return walk_run<int32_t>(w, nx, ny, nz, acc);
+    return walk_run<int64_t>(w, nx, ny, nz, acc);
+}
+
+}  // namespace hullmi

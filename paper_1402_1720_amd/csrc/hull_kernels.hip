@@ -1,0 +1,379 @@
+// Kernels of the hull path for gfx950 (wave64): classify + geometry + walk +
+// accumulate, the SC/MSC/SM rules, and the FDK hull.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hull_device.h"
+#include "hull_kernels.h"
+
+namespace hullmi {
+
+// ---------------------------------------------------------------------------
+// small utilities
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// Block-wide sum of six per-thread counters into the stats struct.
+__device__ __forceinline__ void flush_stats(hullmi_stats *st, unsigned long long l,
+                                            unsigned long long h, unsigned long long sk,
+                                            unsigned long long mi, unsigned long long vl,
+                                            unsigned long long vh)
+{
+    __shared__ unsigned long long s[6];
+    if (threadIdx.x < 6) s[threadIdx.x] = 0;
+    __syncthreads();
+    if (l) atomicAdd(&s[0], l);
+    if (h) atomicAdd(&s[1], h);
+    if (sk) atomicAdd(&s[2], sk);
+    if (mi) atomicAdd(&s[3], mi);
+    if (vl) atomicAdd(&s[4], vl);
+    if (vh) atomicAdd(&s[5], vh);
+    __syncthreads();
+    if (threadIdx.x < 6 && s[threadIdx.x])
+        atomicAdd(reinterpret_cast<unsigned long long *>(st) + threadIdx.x, s[threadIdx.x]);
+}
+
+struct GlobalAcc {
+    int *cnt;
+    __device__ __forceinline__ void operator()(int off) const { atomicAdd(cnt + off, 1); }
+};
+
+// ---------------------------------------------------------------------------
+// classify -> geometry -> walk -> accumulate, one history per lane
+
+__global__ void __launch_bounds__(256)
+k_walk_histories(hullmi_histories h, DevGrid g, float e_low, float e_high, int *N, int *M,
+                 hullmi_stats *st)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long nl = 0, nh = 0, nsk = 0, nmi = 0, vl = 0, vh = 0;
+    if (i < h.n) {
+        const float w = h.wepl[i];
+        if (!isfinite(w)) {
+            nsk = 1;
+        } else {
+            const bool low = N != nullptr && w < e_low;
+            const bool high = M != nullptr && w > e_high;
+            if (low || high) {
+                const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
+                const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
+                const float a = h.angle_deg[i];
+                int qi[3], qo[3];
+                int stg = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) &&
+                           isfinite(yo) && isfinite(zo) && isfinite(a))
+                              ? kGeoOk
+                              : kGeoNonFinite;
+                if (stg == kGeoOk) {
+                    float c, s;
+                    deg_cos_sin(a, c, s);
+                    stg = quantize_point(c, s, xi, yi, zi, g, qi[0], qi[1], qi[2]);
+                    if (stg == kGeoOk) stg = quantize_point(c, s, xo, yo, zo, g, qo[0], qo[1], qo[2]);
+                    if (stg == kGeoOk && qi[0] == qo[0] && qi[1] == qo[1] && qi[2] == qo[2])
+                        stg = kGeoDegenerate;
+                }
+                if (stg != kGeoOk) {
+                    nsk = 1;
+                } else {
+                    GlobalAcc acc{low ? N : M};
+                    const int c = walk_line(qi[0], qi[1], qi[2], qo[0], qo[1], qo[2], g.nx, g.ny,
+                                            g.nz, acc);
+                    if (low) { nl = 1; vl = (unsigned long long)c; }
+                    else { nh = 1; vh = (unsigned long long)c; }
+                    nmi = c == 0;
+                }
+            }
+        }
+    }
+    if (st) flush_stats(st, nl, nh, nsk, nmi, vl, vh);
+}
+
+__global__ void __launch_bounds__(256)
+k_walk_lines(const int *qin, const int *qout, int64_t n, int nx, int ny, int nz, int *cnt,
+             hullmi_stats *st)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long nl = 0, nsk = 0, nmi = 0, vl = 0;
+    if (i < n) {
+        const int a0 = qin[3 * i], a1 = qin[3 * i + 1], a2 = qin[3 * i + 2];
+        const int b0 = qout[3 * i], b1 = qout[3 * i + 1], b2 = qout[3 * i + 2];
+        const int lim = 1 << 26;
+        const bool ok = a0 > -lim && a0 < lim && a1 > -lim && a1 < lim && a2 > -lim && a2 < lim &&
+                        b0 > -lim && b0 < lim && b1 > -lim && b1 < lim && b2 > -lim && b2 < lim &&
+                        !(a0 == b0 && a1 == b1 && a2 == b2);
+        if (!ok) {
+            nsk = 1;
+        } else {
+            GlobalAcc acc{cnt};
+            const int c = walk_line(a0, a1, a2, b0, b1, b2, nx, ny, nz, acc);
+            nl = 1;
+            vl = (unsigned long long)c;
+            nmi = c == 0;
+        }
+    }
+    if (st) flush_stats(st, nl, 0, nsk, nmi, vl, 0);
+}
+
+__global__ void __launch_bounds__(256)
+k_quantize(hullmi_histories h, DevGrid g, int *status, int *qin, int *qout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h.n) return;
+    const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
+    const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
+    const float a = h.angle_deg[i], w = h.wepl[i];
+    int st = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
+              isfinite(zo) && isfinite(a) && isfinite(w))
+                 ? kGeoOk
+                 : kGeoNonFinite;
+    int q[6];
+    if (st == kGeoOk) {
+        float c, s;
+        deg_cos_sin(a, c, s);
+        st = quantize_point(c, s, xi, yi, zi, g, q[0], q[1], q[2]);
+        if (st == kGeoOk) st = quantize_point(c, s, xo, yo, zo, g, q[3], q[4], q[5]);
+        if (st == kGeoOk && q[0] == q[3] && q[1] == q[4] && q[2] == q[5]) st = kGeoDegenerate;
+    }
+    status[i] = st;
+    if (st == kGeoOk || st == kGeoDegenerate) {
+        qin[3 * i] = q[0]; qin[3 * i + 1] = q[1]; qin[3 * i + 2] = q[2];
+        qout[3 * i] = q[3]; qout[3 * i + 1] = q[4]; qout[3 * i + 2] = q[5];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// hull rules
+
+__device__ __forceinline__ void voxel_ijk(int64_t v, int nx, int ny, int &i, int &j, int &k)
+{
+    i = (int)(v % nx);
+    const int64_t r = v / nx;
+    j = (int)(r % ny);
+    k = (int)(r / ny);
+}
+
+__global__ void k_sc_mask(const int *N, uint8_t *mask, int64_t V)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < V) mask[v] = N[v] == 0;
+}
+
+// MSC: COUNT keeps N < n_t; NEIGHBOR_DIFF removes v when N(v) - N(w) >= n_t
+// for a face neighbour w (in-plane, or 3-D with nbr == SPATIAL6).
+__global__ void k_msc_mask(const int *N, uint8_t *mask, int nx, int ny, int nz, int n_t,
+                           int mode, int nbr)
+{
+    const int64_t V = (int64_t)nx * ny * nz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int64_t nv = N[v];
+    if (mode == HULL_MSC_COUNT) {
+        mask[v] = nv < n_t;
+        return;
+    }
+    int i, j, k;
+    voxel_ijk(v, nx, ny, i, j, k);
+    int64_t lo = nv;   // smallest neighbour count (v itself included)
+    if (i > 0) lo = min(lo, (int64_t)N[v - 1]);
+    if (i < nx - 1) lo = min(lo, (int64_t)N[v + 1]);
+    if (j > 0) lo = min(lo, (int64_t)N[v - nx]);
+    if (j < ny - 1) lo = min(lo, (int64_t)N[v + nx]);
+    if (nbr == HULL_NBR_SPATIAL6) {
+        const int64_t pl = (int64_t)nx * ny;
+        if (k > 0) lo = min(lo, (int64_t)N[v - pl]);
+        if (k < nz - 1) lo = min(lo, (int64_t)N[v + pl]);
+    }
+    mask[v] = nv - lo < n_t;
+}
+
+// Largest value per segment (segments of seg_len voxels) with one atomicMax
+// per block and segment.
+__global__ void __launch_bounds__(256)
+k_seg_max(const int *M, unsigned long long *out, int64_t V, int64_t seg_len)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    atomicMax(out + v / seg_len, (unsigned long long)(unsigned)M[v]);
+}
+
+// Algorithm 3's maximum slope: per voxel the largest M(v) - M(w) over B(v)
+// (0 from w = v), packed with the voxel index so that the 64-bit maximum
+// picks the largest slope and, among equal slopes, the last voxel.
+__global__ void __launch_bounds__(256)
+k_seg_slope_argmax(const int *M, unsigned long long *out, int nx, int ny, int nz, int nbr,
+                   int64_t seg_len)
+{
+    const int64_t V = (int64_t)nx * ny * nz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int i, j, k;
+    voxel_ijk(v, nx, ny, i, j, k);
+    const int64_t mv = M[v];
+    int64_t lo = mv;
+    if (i > 0) lo = min(lo, (int64_t)M[v - 1]);
+    if (i < nx - 1) lo = min(lo, (int64_t)M[v + 1]);
+    if (j > 0) lo = min(lo, (int64_t)M[v - nx]);
+    if (j < ny - 1) lo = min(lo, (int64_t)M[v + nx]);
+    if (nbr == HULL_NBR_SPATIAL6) {
+        const int64_t pl = (int64_t)nx * ny;
+        if (k > 0) lo = min(lo, (int64_t)M[v - pl]);
+        if (k < nz - 1) lo = min(lo, (int64_t)M[v + pl]);
+    }
+    const unsigned long long key = ((unsigned long long)(mv - lo) << 32) | (unsigned long long)v;
+    atomicMax(out + v / seg_len, key);
+}
+
+__global__ void k_sm_mask(const int *M, uint8_t *mask, int64_t V, int64_t seg_len, int mode,
+                          int num, int den, const unsigned long long *seg)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const unsigned long long s = seg[v / seg_len];
+    const int64_t mv = M[v];
+    if (mode == HULL_SM_FRACTION) {
+        mask[v] = (int64_t)den * mv > (int64_t)num * (int64_t)s;
+    } else {
+        const int64_t mt = M[(int64_t)(s & 0xffffffffull)];
+        mask[v] = mv > mt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FDK hull
+
+// Bin each history where its line crosses x = 0; WEPL sums in fixed point
+// (2^-16 mm) so the result does not depend on the order of the atomics.
+__global__ void __launch_bounds__(256)
+k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h.n) return;
+    const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
+    const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
+    const float a = h.angle_deg[i], w = h.wepl[i];
+    if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
+          isfinite(zo) && isfinite(a) && isfinite(w)))
+        return;
+    if (!(fabsf(w) < 65536.0f)) return;
+    const float ddx = xo - xi;
+    if (ddx == 0.0f) return;
+    const float r = (0.0f - xi) / ddx;
+    const float u = yi + r * (yo - yi);
+    const float v = zi + r * (zo - zi);
+    const float fa = (a - p.angle0) * p.rda;
+    const float fu = (u - p.u0) * p.rdu;
+    const float fv = (v - p.v0) * p.rdv;
+    if (!(fabsf(fa) < 1.0e9f)) return;
+    if (!(fu >= 0.0f && fu < (float)p.nu && fv >= 0.0f && fv < (float)p.nv)) return;
+    long long k = (long long)rintf(fa) % p.n_angles;
+    if (k < 0) k += p.n_angles;
+    const int iu = (int)floorf(fu), iv = (int)floorf(fv);
+    const int64_t b = ((int64_t)k * p.nv + iv) * p.nu + iu;
+    const long long fx = llrint((double)w * 65536.0);
+    atomicAdd(sum + b, (unsigned long long)fx);
+    atomicAdd(cnt + b, 1u);
+}
+
+// One block per detector row: bin means, cosine pre-weight, then the
+// Shepp-Logan convolution along u (FP64 accumulation, rows taken as zero
+// outside the detector).
+__global__ void __launch_bounds__(256)
+k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p)
+{
+    extern __shared__ double sh[];
+    const int nu = p.nu;
+    double *row = sh;             // nu
+    double *ker = sh + nu;        // 2 nu - 1, ker[m + nu - 1] = h[m]
+    const int64_t r = blockIdx.x; // k * nv + iv
+    const int iv = (int)(r % p.nv);
+    const double D = p.src_dist, du = p.du;
+    const double vc = (double)p.v0 + ((double)iv + 0.5) * (double)p.dv;
+    const double pi = 3.14159265358979323846;
+    for (int iu = threadIdx.x; iu < nu; iu += blockDim.x) {
+        const int64_t b = r * nu + iu;
+        const unsigned c = cnt[b];
+        const double mean = c ? (double)(long long)sum[b] * (1.0 / 65536.0) / (double)c : 0.0;
+        const double uc = (double)p.u0 + ((double)iu + 0.5) * du;
+        row[iu] = mean * D / sqrt(D * D + uc * uc + vc * vc);
+    }
+    for (int m = threadIdx.x; m < 2 * nu - 1; m += blockDim.x) {
+        const double n = (double)(m - (nu - 1));
+        ker[m] = -2.0 / (pi * pi * du * du * (4.0 * n * n - 1.0));
+    }
+    __syncthreads();
+    for (int iu = threadIdx.x; iu < nu; iu += blockDim.x) {
+        double acc = 0.0;
+        const double *kr = ker + iu + nu - 1;
+        for (int j = 0; j < nu; ++j) acc += kr[-j] * row[j];
+        q[r * nu + iu] = (float)(du * acc);
+    }
+}
+
+__global__ void k_fbp_trig(float2 *cs, FbpDev p)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= p.n_angles) return;
+    const double th = ((double)p.angle0 + (double)k * (double)p.dangle) * (3.14159265358979323846 / 180.0);
+    cs[k] = make_float2((float)cos(th), (float)sin(th));
+}
+
+// FDK backprojection, one voxel per lane, all angles; threshold fused.
+__global__ void __launch_bounds__(256)
+k_fbp_backproject(const float *q, const float2 *cs, FbpDev p, FbpGridDev g, float *image,
+                  uint8_t *mask)
+{
+    const int64_t V = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int i, j, k;
+    voxel_ijk(v, g.nx, g.ny, i, j, k);
+    const float xo = g.x0 + ((float)i + 0.5f) * g.dx;
+    const float yo = g.y0 + ((float)j + 0.5f) * g.dy;
+    const float zo = g.z0 + ((float)k + 0.5f) * g.dz;
+    const float D = p.src_dist, rD = 1.0f / p.src_dist;
+    const int nu = p.nu, nv = p.nv;
+    float f = 0.0f;
+    for (int a = 0; a < p.n_angles; ++a) {
+        const float2 t = cs[a];
+        const float xl = t.x * xo - t.y * yo;
+        const float yl = t.y * xo + t.x * yo;
+        const float U = (D + xl) * rD;
+        if (!(U > 0.0f)) continue;   // voxel at or behind the source plane
+        const float iU = 1.0f / U;
+        const float fu = (yl * iU - p.u0) * p.rdu - 0.5f;
+        const float fv = (zo * iU - p.v0) * p.rdv - 0.5f;
+        if (!(fabsf(fu) < 1.0e8f && fabsf(fv) < 1.0e8f)) continue;
+        const float fu0 = floorf(fu), fv0 = floorf(fv);
+        const float au = fu - fu0, av = fv - fv0;
+        const int iu0 = (int)fu0, iv0 = (int)fv0;
+        const float *qa = q + (int64_t)a * nv * nu;
+        float val = 0.0f;
+        if (iv0 >= 0 && iv0 < nv) {
+            const float *qr = qa + (int64_t)iv0 * nu;
+            const float l = (iu0 >= 0 && iu0 < nu) ? qr[iu0] : 0.0f;
+            const float r = (iu0 + 1 >= 0 && iu0 + 1 < nu) ? qr[iu0 + 1] : 0.0f;
+            val += (1.0f - av) * ((1.0f - au) * l + au * r);
+        }
+        if (iv0 + 1 >= 0 && iv0 + 1 < nv) {
+            const float *qr = qa + (int64_t)(iv0 + 1) * nu;
+            const float l = (iu0 >= 0 && iu0 < nu) ? qr[iu0] : 0.0f;
+            const float r = (iu0 + 1 >= 0 && iu0 + 1 < nu) ? qr[iu0 + 1] : 0.0f;
+            val += av * ((1.0f - au) * l + au * r);
+        }
+        f += val * iU * iU;
+    }
+    f *= p.half_dth;
+    image[v] = f;
+    if (mask) mask[v] = f >= p.threshold;
+}
+
+}  // namespace hullmi

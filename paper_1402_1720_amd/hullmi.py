@@ -1,0 +1,319 @@
+"""ctypes binding of ``libhullmi.so`` (C ABI in ``include/hullmi.h``).
+
+Argument marshalling only: every step of the hull path runs in the HIP
+library. torch tensors provide device memory and streams. Sizes, dtypes and
+devices are checked here, because the C ABI takes bare pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Dict, Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhullmi.so")
+
+HULL_OK, HULL_EINVAL, HULL_ENOMEM, HULL_EDEVICE, HULL_EBUSY, HULL_ENOTSUP, HULL_ETIMEDOUT = range(7)
+HULL_ACCUMULATE = 1
+HULL_MSC_COUNT, HULL_MSC_NEIGHBOR_DIFF = 0, 1
+HULL_SM_FRACTION, HULL_SM_MAX_SLOPE = 0, 1
+HULL_SCOPE_VOLUME, HULL_SCOPE_SLICE = 0, 1
+HULL_NBR_INPLANE4, HULL_NBR_SPATIAL6 = 0, 1
+HULL_OP_SC, HULL_OP_MSC, HULL_OP_SM, HULL_OP_ALL, HULL_OP_FBP, HULL_OP_COUNT_LINES = range(6)
+
+FIELDS = ("x_in", "y_in", "z_in", "x_out", "y_out", "z_out", "angle_deg", "wepl")
+
+
+class hullmi_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_float), ("dy", ctypes.c_float), ("dz", ctypes.c_float),
+                ("x0", ctypes.c_float), ("y0", ctypes.c_float), ("z0", ctypes.c_float)]
+
+
+class hullmi_histories(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in FIELDS] + [("n", ctypes.c_int64)]
+
+
+class hullmi_params(ctypes.Structure):
+    _fields_ = [("wepl_low", ctypes.c_float), ("wepl_high", ctypes.c_float),
+                ("msc_n_t", ctypes.c_int32), ("msc_mode", ctypes.c_int32),
+                ("sm_frac_num", ctypes.c_int32), ("sm_frac_den", ctypes.c_int32),
+                ("sm_mode", ctypes.c_int32), ("sm_scope", ctypes.c_int32), ("nbr", ctypes.c_int32)]
+
+
+class hullmi_fbp_params(ctypes.Structure):
+    _fields_ = [("src_dist_mm", ctypes.c_float), ("du_mm", ctypes.c_float),
+                ("dv_mm", ctypes.c_float), ("u0_mm", ctypes.c_float), ("v0_mm", ctypes.c_float),
+                ("nu", ctypes.c_int32), ("nv", ctypes.c_int32), ("n_angles", ctypes.c_int32),
+                ("angle0_deg", ctypes.c_float), ("dangle_deg", ctypes.c_float),
+                ("filter", ctypes.c_int32), ("threshold", ctypes.c_float)]
+
+
+# every symbol the header declares, with its ctypes signature
+_P, _I32, _I64, _U32, _F, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                 ctypes.c_float, ctypes.c_size_t)
+SIGNATURES = {
+    "hull_abi_version": ([], ctypes.c_int),
+    "hull_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "hull_workspace_bytes": ([ctypes.c_int, _P, _I64, _P], _SZ),
+    "hull_sc": ([_P, _P, _F, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
+    "hull_msc": ([_P, _P, _F, _I32, ctypes.c_int, ctypes.c_int, _P, _P, _U32, _P, _P, _SZ, _P],
+                 ctypes.c_int),
+    "hull_sm": ([_P, _P, _F, _I32, _I32, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _U32,
+                 _P, _P, _SZ, _P], ctypes.c_int),
+    "hull_all": ([_P, _P, _P, _P, _P, _P, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
+    "hull_fbp": ([_P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "hull_count_lines": ([_P, _P, _I64, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
+    "hull_quantize": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+}
+
+_lib_handle = None
+
+
+def lib():
+    """The loaded HIP library. Raises if it has not been built: there is no
+    other implementation to fall back to."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1402_1720_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib_handle = L
+    return _lib_handle
+
+
+class HullError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {hull_strerror(status)} (status {status})")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != HULL_OK:
+        raise HullError(rc, where)
+
+
+def hull_abi_version() -> int:
+    return lib().hull_abi_version()
+
+
+def hull_strerror(status: int) -> str:
+    return lib().hull_strerror(int(status)).decode()
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+
+def make_grid(g) -> hullmi_grid:
+    """``hullmi_grid`` from a ``hullmi_grid`` or any object with ``n``, ``d`` and
+    ``origin`` triples (lower corner of voxel (0,0,0))."""
+    if isinstance(g, hullmi_grid):
+        return g
+    return hullmi_grid(int(g.n[0]), int(g.n[1]), int(g.n[2]), float(g.d[0]), float(g.d[1]),
+                       float(g.d[2]), float(g.origin[0]), float(g.origin[1]), float(g.origin[2]))
+
+
+def _voxels(g: hullmi_grid) -> int:
+    return int(g.nx) * int(g.ny) * int(g.nz)
+
+
+def _dev_ptr(t: Optional[torch.Tensor], dtype: torch.dtype, numel: Optional[int], name: str,
+             device: Optional[torch.device] = None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Histories:
+    """Eight FP32 device arrays of one length (SoA), as ``hullmi_histories``."""
+
+    def __init__(self, arrays: Dict[str, torch.Tensor]):
+        self.arrays = {k: arrays[k] for k in FIELDS}
+        n = self.arrays["wepl"].numel()
+        dev = self.arrays["wepl"].device
+        ptrs = {k: _dev_ptr(v, torch.float32, n, k, dev) for k, v in self.arrays.items()}
+        self.n = n
+        self.device = dev
+        self.c = hullmi_histories(*[ptrs[k].value if n else None for k in FIELDS], n)
+
+    @classmethod
+    def from_numpy(cls, arrays, device="cuda") -> "Histories":
+        return cls({k: torch.from_numpy(arrays[k]).to(device) for k in FIELDS})
+
+    def slice(self, a: int, b: int) -> "Histories":
+        return Histories({k: v[a:b] for k, v in self.arrays.items()})
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def hull_workspace_bytes(op: int, grid, n: int, fbp: Optional[hullmi_fbp_params] = None) -> int:
+    g = make_grid(grid)
+    r = lib().hull_workspace_bytes(int(op), ctypes.byref(g), int(n),
+                                   ctypes.byref(fbp) if fbp is not None else None)
+    if r == ctypes.c_size_t(-1).value:
+        raise HullError(HULL_EINVAL, "hull_workspace_bytes")
+    return int(r)
+
+
+def workspace(op: int, grid, n: int, device, fbp=None) -> Optional[torch.Tensor]:
+    nbytes = hull_workspace_bytes(op, grid, n, fbp)
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device) if nbytes else None
+
+
+def _ws(ws: Optional[torch.Tensor]):
+    if ws is None:
+        return None, 0
+    return _dev_ptr(ws, torch.uint8, None, "ws"), ws.numel()
+
+
+def _stats_ptr(stats):
+    return _dev_ptr(stats, torch.int64, 6, "stats")
+
+
+STATS_FIELDS = ("n_low", "n_high", "n_skipped", "n_missed_grid", "n_visits_low", "n_visits_high")
+
+
+def stats_dict(stats: torch.Tensor) -> Dict[str, int]:
+    v = stats.cpu().tolist()
+    return dict(zip(STATS_FIELDS, (int(x) for x in v)))
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+
+def hull_sc(hist: Histories, grid, wepl_low: float, N: torch.Tensor,
+            mask: Optional[torch.Tensor] = None, flags: int = 0,
+            stats: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    g = make_grid(grid)
+    V = _voxels(g)
+    wp, wn = _ws(ws)
+    rc = lib().hull_sc(ctypes.byref(hist.c), ctypes.byref(g), float(wepl_low),
+                       _dev_ptr(N, torch.int32, V, "N", hist.device),
+                       _dev_ptr(mask, torch.uint8, V, "mask", hist.device), int(flags),
+                       _stats_ptr(stats), wp, wn, _stream(stream))
+    _check(rc, "hull_sc")
+
+
+def hull_msc(hist: Histories, grid, wepl_low: float, n_t: int, mode: int, nbr: int,
+             N: torch.Tensor, mask: Optional[torch.Tensor] = None, flags: int = 0,
+             stats: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    g = make_grid(grid)
+    V = _voxels(g)
+    wp, wn = _ws(ws)
+    rc = lib().hull_msc(ctypes.byref(hist.c), ctypes.byref(g), float(wepl_low), int(n_t), int(mode),
+                        int(nbr), _dev_ptr(N, torch.int32, V, "N", hist.device),
+                        _dev_ptr(mask, torch.uint8, V, "mask", hist.device), int(flags),
+                        _stats_ptr(stats), wp, wn, _stream(stream))
+    _check(rc, "hull_msc")
+
+
+def hull_sm(hist: Histories, grid, wepl_high: float, frac_num: int, frac_den: int, mode: int,
+            scope: int, nbr: int, M: torch.Tensor, mask: Optional[torch.Tensor] = None,
+            flags: int = 0, stats: Optional[torch.Tensor] = None,
+            ws: Optional[torch.Tensor] = None, stream=None):
+    g = make_grid(grid)
+    V = _voxels(g)
+    if ws is None and mask is not None:
+        ws = workspace(HULL_OP_SM, g, hist.n, hist.device)
+    wp, wn = _ws(ws)
+    rc = lib().hull_sm(ctypes.byref(hist.c), ctypes.byref(g), float(wepl_high), int(frac_num),
+                       int(frac_den), int(mode), int(scope), int(nbr),
+                       _dev_ptr(M, torch.int32, V, "M", hist.device),
+                       _dev_ptr(mask, torch.uint8, V, "mask", hist.device), int(flags),
+                       _stats_ptr(stats), wp, wn, _stream(stream))
+    _check(rc, "hull_sm")
+
+
+def make_params(wepl_low=1.0, wepl_high=5.0, msc_n_t=5, msc_mode=HULL_MSC_COUNT, sm_frac_num=3,
+                sm_frac_den=5, sm_mode=HULL_SM_FRACTION, sm_scope=HULL_SCOPE_VOLUME,
+                nbr=HULL_NBR_INPLANE4) -> hullmi_params:
+    return hullmi_params(wepl_low, wepl_high, msc_n_t, msc_mode, sm_frac_num, sm_frac_den, sm_mode,
+                         sm_scope, nbr)
+
+
+def hull_all(hist: Histories, grid, params: hullmi_params, N: torch.Tensor, M: torch.Tensor,
+             sc_mask=None, msc_mask=None, sm_mask=None, flags: int = 0, stats=None, ws=None,
+             stream=None):
+    g = make_grid(grid)
+    V = _voxels(g)
+    if ws is None:
+        ws = workspace(HULL_OP_ALL, g, hist.n, hist.device)
+    wp, wn = _ws(ws)
+    d = hist.device
+    rc = lib().hull_all(ctypes.byref(hist.c), ctypes.byref(g), ctypes.byref(params),
+                        _dev_ptr(N, torch.int32, V, "N", d), _dev_ptr(M, torch.int32, V, "M", d),
+                        _dev_ptr(sc_mask, torch.uint8, V, "sc_mask", d),
+                        _dev_ptr(msc_mask, torch.uint8, V, "msc_mask", d),
+                        _dev_ptr(sm_mask, torch.uint8, V, "sm_mask", d), int(flags),
+                        _stats_ptr(stats), wp, wn, _stream(stream))
+    _check(rc, "hull_all")
+
+
+def make_fbp_params(geo) -> hullmi_fbp_params:
+    """``hullmi_fbp_params`` from an object with src_dist, du, dv, u0, v0, nu, nv,
+    n_angles, angle0, dangle and threshold attributes."""
+    return hullmi_fbp_params(geo.src_dist, geo.du, geo.dv, geo.u0, geo.v0, geo.nu, geo.nv,
+                             geo.n_angles, geo.angle0, geo.dangle, 0, geo.threshold)
+
+
+def hull_fbp(hist: Histories, grid, fbp: hullmi_fbp_params, image: torch.Tensor,
+             mask: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    g = make_grid(grid)
+    V = _voxels(g)
+    if ws is None:
+        ws = workspace(HULL_OP_FBP, g, hist.n, hist.device, fbp)
+    wp, wn = _ws(ws)
+    d = hist.device
+    rc = lib().hull_fbp(ctypes.byref(hist.c), ctypes.byref(g), ctypes.byref(fbp),
+                        _dev_ptr(image, torch.float32, V, "image", d),
+                        _dev_ptr(mask, torch.uint8, V, "mask", d), wp, wn, _stream(stream))
+    _check(rc, "hull_fbp")
+
+
+def hull_count_lines(q_in: torch.Tensor, q_out: torch.Tensor, grid, counts: torch.Tensor,
+                     flags: int = 0, stats=None, ws=None, stream=None):
+    g = make_grid(grid)
+    n = q_in.numel() // 3
+    if q_in.numel() != 3 * n or q_out.numel() != 3 * n:
+        raise ValueError("q_in and q_out must be [n, 3]")
+    d = counts.device
+    wp, wn = _ws(ws)
+    rc = lib().hull_count_lines(_dev_ptr(q_in, torch.int32, 3 * n, "q_in", d),
+                                _dev_ptr(q_out, torch.int32, 3 * n, "q_out", d), n,
+                                ctypes.byref(g), _dev_ptr(counts, torch.int32, _voxels(g), "counts", d),
+                                int(flags), _stats_ptr(stats), wp, wn, _stream(stream))
+    _check(rc, "hull_count_lines")
+
+
+def hull_quantize(hist: Histories, grid, status: torch.Tensor, q_in: torch.Tensor,
+                  q_out: torch.Tensor, stream=None):
+    g = make_grid(grid)
+    n = hist.n
+    d = hist.device
+    rc = lib().hull_quantize(ctypes.byref(hist.c), ctypes.byref(g),
+                             _dev_ptr(status, torch.int32, n, "status", d),
+                             _dev_ptr(q_in, torch.int32, 3 * n, "q_in", d),
+                             _dev_ptr(q_out, torch.int32, 3 * n, "q_out", d), _stream(stream))
+    _check(rc, "hull_quantize")

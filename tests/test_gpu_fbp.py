@@ -1,0 +1,70 @@
+"""GPU parity of the FDK hull (Section 3.1): FP32 image within 1e-4 of the
+FP64 oracle's maximum |f|, masks equal except where the oracle's value lies
+within that tolerance of the threshold."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from paper_1402_1720_amd import hullmi as H
+from tests.test_oracle_fbp import _bin_centre_rays
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+TOL = 1e-4
+
+
+def _run(h, grid, geo):
+    V = grid.voxels
+    img = torch.zeros(V, dtype=torch.float32, device=DEV)
+    mask = torch.zeros(V, dtype=torch.uint8, device=DEV)
+    H.hull_fbp(H.Histories.from_numpy(h, DEV), grid, H.make_fbp_params(geo), img, mask)
+    torch.cuda.synchronize()
+    ref, rmask, _, _ = oracle.fbp(h, oracle.grid_of(grid), oracle.fbp_params(geo))
+    return img.cpu().numpy().astype(np.float64), mask.cpu().numpy(), ref, rmask
+
+
+def _check(img, mask, ref, rmask, thr):
+    scale = np.abs(ref).max()
+    err = np.abs(img - ref).max() / scale
+    assert err <= TOL, err
+    near = np.abs(ref - thr) <= TOL * scale
+    assert np.array_equal(mask[~near], rmask[~near])
+    return err
+
+
+def test_fbp_cone_beam_sphere():
+    geo, h = _bin_centre_rays(150.0, 30.0, nu=160, nv=12, n_angles=360)
+    grid = gen.Grid((64, 64, 4), (1.0, 1.0, 1.0))
+    img, mask, ref, rmask = _run(h, grid, geo)
+    _check(img, mask, ref, rmask, geo.threshold)
+
+
+def test_fbp_config2_full():
+    """The benchmark workload: 200x200x32, 1e7 noisy histories, 180 angles,
+    1 mm x 5 mm detector bins, Shepp-Logan, threshold 0.6."""
+    spec = gen.config_spec(2)
+    h = gen.generate(spec)
+    geo = spec.fbp_geometry(du=1.0, dv=5.0)
+    img, mask, ref, rmask = _run(h, spec.grid, geo)
+    err = _check(img, mask, ref, rmask, geo.threshold)
+    print("config2 FBP max rel err", err, flush=True)
+    # the hull keeps the head
+    cen = gen.voxel_centres(spec.grid).reshape(-1, 3)
+    inside = gen.phantom_rsp(spec.phantom[:1], cen * 1.1) > 0
+    assert mask[inside].mean() > 0.99
+
+
+def test_fbp_edge_histories():
+    spec = gen.config_spec(1, n_hist=5000)
+    h = gen.generate(spec)
+    h = {k: v.copy() for k, v in h.items()}
+    h["wepl"][0] = np.float32("nan")
+    h["wepl"][1] = 70000.0          # beyond 2^16 mm: not binned
+    h["x_out"][2] = h["x_in"][2]    # parallel to the detector plane
+    h["y_in"][3] = 1e9              # off the detector
+    h["angle_deg"][4] = 3e9         # cannot be binned
+    geo = spec.fbp_geometry(du=1.0, dv=2.5)
+    img, mask, ref, rmask = _run(h, spec.grid, geo)
+    _check(img, mask, ref, rmask, geo.threshold)
