@@ -3,10 +3,12 @@
 // only enqueues work on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 
+#include "hull_binned.h"
 #include "hull_device.h"
 #include "hull_kernels.h"
 #include "hullmi.h"
@@ -100,6 +102,90 @@ void fill_u64(void *p, unsigned long long v, int64_t n, hipStream_t s)
 // Workspace of the SM rules: one 64-bit slot per z-slice (covers both scopes).
 size_t sm_ws_bytes(const hullmi_grid *g) { return align_up((size_t)g->nz * 8); }
 
+// Device properties the launch shapes depend on (queried per call: cheap).
+struct DevProps {
+    size_t max_lds;
+    int cus;
+};
+
+DevProps dev_props()
+{
+    DevProps p{65536, 256};
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return p;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+        p.max_lds = (size_t)v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+        p.cus = v;
+    return p;
+}
+
+inline int64_t plane_of(const hullmi_grid *g) { return (int64_t)g->nx * g->ny; }
+
+// A slice fits the LDS tile when its 16-bit counters fit kMaxTileVoxels.
+inline bool tile_fits(const hullmi_grid *g) { return plane_of(g) <= kMaxTileVoxels; }
+
+// Length classes per slice: up to 16, fewer when there are many slices, so
+// that the sub-bin histogram of a block fits its LDS.
+inline int length_classes(const hullmi_grid *g) { return std::max(1, std::min(16, 2048 / g->nz)); }
+
+// Workgroups of the persistent walk (and the least number of ranges).
+constexpr int kMinRanges = 1024;
+
+// Layout of the slice-binned counting workspace for batches of up to
+// min(n, kBatch) histories. With base == nullptr only the size is computed.
+BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
+{
+    BinWs w;
+    const int64_t B = std::max<int64_t>(1, std::min<int64_t>(n, kBatch));
+    w.B = B;
+    w.nz = g->nz;
+    w.nl = length_classes(g);
+    w.lwidth = std::max(1, (g->nx + g->ny + w.nl - 1) / w.nl);
+    w.ntiles = 2 * g->nz;
+    w.nsub = w.ntiles * w.nl + 2;
+    w.nblk = (int)((B + kHistPerBlock - 1) / kHistPerBlock);
+    w.tile_words = tile_fits(g) ? (int)((plane_of(g) + 1) / 2) : 1;
+    w.min_ranges = kMinRanges;
+    // ranges: P0 = max(min_ranges, ceil(I / 32768)) coarse ranges, each split
+    // into at most ceil(items / 32768) pieces: P <= 2 P0 + I / 32768
+    const int64_t imax = B * kMaxSlicesPerLine;
+    const int64_t p0 = std::max<int64_t>(kMinRanges, (imax + kItemsPerRange - 1) / kItemsPerRange);
+    w.max_ranges = (int)(2 * p0 + (imax + kItemsPerRange - 1) / kItemsPerRange);
+    w.max_slots = w.max_ranges + w.ntiles;
+    char *b = reinterpret_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t nbytes) {
+        char *p = b ? b + off : nullptr;
+        off += align_up(nbytes);
+        return p;
+    };
+    w.q = reinterpret_cast<int32_t *>(take((size_t)B * 24));
+    w.meta = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
+    w.lpack = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
+    w.blk = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.nblk * 4));
+    w.sub_total = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * 4));
+    w.sub_start = reinterpret_cast<uint32_t *>(take((size_t)(w.nsub + 1) * 4));
+    w.tile_start = reinterpret_cast<uint32_t *>(take((size_t)(w.ntiles + 1) * 4));
+    w.range_start = reinterpret_cast<uint32_t *>(take((size_t)(w.max_ranges + 1) * 4));
+    w.range_coarse = reinterpret_cast<uint32_t *>(take((size_t)(w.max_ranges + 1) * 4));
+    w.range_piece = reinterpret_cast<uint32_t *>(take((size_t)(w.max_ranges + 1) * 4));
+    w.wprefix = reinterpret_cast<unsigned long long *>(take((size_t)(w.nsub + 1) * 8));
+    w.ctl = reinterpret_cast<int32_t *>(take((size_t)kCtlWords * 4));
+    w.items = reinterpret_cast<uint32_t *>(take((size_t)imax * 4));
+    w.partial = reinterpret_cast<uint32_t *>(
+        take(tile_fits(g) ? (size_t)w.max_slots * w.tile_words * 4 : 0));
+    if (bytes) *bytes = off;
+    return w;
+}
+
+size_t counts_ws_bytes(const hullmi_grid *g, int64_t n)
+{
+    size_t bytes = 0;
+    bin_ws_layout(g, n, nullptr, &bytes);
+    return bytes;
+}
+
 struct FbpWs {
     unsigned long long *sum;
     unsigned *cnt;
@@ -123,8 +209,9 @@ FbpWs fbp_ws_layout(const hullmi_fbp_params *p, void *base)
 }
 
 // Zero (unless accumulating) and count: the shared core of every hull call.
+// Histories go through in batches of up to kBatch; counts add up across them.
 int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, float e_high, int32_t *N,
-               int32_t *M, uint32_t flags, hullmi_stats *stats, hipStream_t s)
+               int32_t *M, uint32_t flags, hullmi_stats *stats, void *ws, hipStream_t s)
 {
     const int64_t V = voxels(g);
     if (!(flags & HULL_ACCUMULATE)) {
@@ -132,9 +219,41 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         fill_u32(M, 0u, M ? V : 0, s);
         fill_u64(stats, 0ull, stats ? 6 : 0, s);
     }
-    if (h->n > 0) {
-        k_walk_histories<<<blocks_for(h->n), kBlock, 0, s>>>(*h, dev_grid(g), e_low, e_high, N, M,
-                                                            stats);
+    if (h->n == 0) return launch_status();
+    BinWs w = bin_ws_layout(g, h->n, ws, nullptr);
+    const DevProps dp = dev_props();
+    const size_t tile_bytes = (size_t)w.tile_words * 4 + 16;   // tile + control words
+    const bool tile_ok = tile_fits(g) && tile_bytes <= dp.max_lds;
+    int per_cu = 1;
+    if (tile_ok) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_walk_tiles),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_bytes);
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_walk_tiles, kTileThreads,
+                                                         tile_bytes) == hipSuccess && occ > 0)
+            per_cu = occ;
+    }
+    const int walk_grid = std::min(dp.cus * per_cu, kMinRanges);
+    const DevGrid dg = dev_grid(g);
+    const int plane = (int)plane_of(g);
+    for (int64_t h0 = 0; h0 < h->n; h0 += w.B) {
+        const int64_t nb = std::min<int64_t>(w.B, h->n - h0);
+        BinWs wb = w;
+        wb.nblk = (int)((nb + kHistPerBlock - 1) / kHistPerBlock);
+        wb.min_ranges = walk_grid;   // one range per resident workgroup at least
+        k_bin_classify<<<wb.nblk, kBinThreads, 0, s>>>(*h, h0, nb, dg, e_low, e_high, N != nullptr,
+                                                       M != nullptr, tile_ok ? 1 : 0, wb, stats);
+        k_bin_scan_blocks<<<wb.nsub, 256, 0, s>>>(wb);
+        k_bin_plan<<<1, 1024, 0, s>>>(wb);
+        k_bin_scatter<<<wb.nblk, kBinThreads, 0, s>>>(nb, wb);
+        if (tile_ok) {
+            k_walk_tiles<<<walk_grid, kTileThreads, tile_bytes, s>>>(wb, g->nx, g->ny);
+            dim3 rg((unsigned)((wb.tile_words + 255) / 256), (unsigned)wb.ntiles);
+            k_reduce_tiles<<<rg, 256, 0, s>>>(wb, plane, N, M, stats);
+        }
+        k_walk_overflow<<<1024, 256, 0, s>>>(wb, g->nx, g->ny, g->nz, N, M, stats);
+        const int rc = launch_status();
+        if (rc != HULL_OK) return rc;
     }
     return launch_status();
 }
@@ -157,10 +276,13 @@ int run_sm_mask(const hullmi_grid *g, const int32_t *M, uint8_t *mask, int num, 
     const int64_t nseg = V / seg_len;
     auto *seg = reinterpret_cast<unsigned long long *>(ws);
     fill_u64(seg, 0ull, nseg, s);
+    // a few blocks per segment, each striding over it with one atomic at the end
+    const unsigned per_seg = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, seg_len / (kBlock * 8)));
+    const dim3 rg(per_seg, (unsigned)nseg);
     if (mode == HULL_SM_FRACTION)
-        k_seg_max<<<blocks_for(V), kBlock, 0, s>>>(M, seg, V, seg_len);
+        k_seg_max<<<rg, kBlock, 0, s>>>(M, seg, V, seg_len);
     else
-        k_seg_slope_argmax<<<blocks_for(V), kBlock, 0, s>>>(M, seg, g->nx, g->ny, g->nz, nbr, seg_len);
+        k_seg_slope_argmax<<<rg, kBlock, 0, s>>>(M, seg, g->nx, g->ny, g->nz, nbr, seg_len);
     k_sm_mask<<<blocks_for(V), kBlock, 0, s>>>(M, mask, V, seg_len, mode, num, den, seg);
     return launch_status();
 }
@@ -205,15 +327,17 @@ size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n, const hu
 {
     if (n < 0) return (size_t)-1;
     switch (op) {
-    case HULL_OP_SC:
-    case HULL_OP_MSC:
     case HULL_OP_COUNT_LINES:
         if (!grid_ok(grid)) return (size_t)-1;
         return 0;
+    case HULL_OP_SC:
+    case HULL_OP_MSC:
+        if (!grid_ok(grid)) return (size_t)-1;
+        return counts_ws_bytes(grid, n);
     case HULL_OP_SM:
     case HULL_OP_ALL:
         if (!grid_ok(grid)) return (size_t)-1;
-        return sm_ws_bytes(grid);
+        return counts_ws_bytes(grid, n) + sm_ws_bytes(grid);
     case HULL_OP_FBP:
         if (!grid_ok(grid) || !fbp_ok(fbp)) return (size_t)-1;
         return fbp_ws_layout(fbp, nullptr).bytes;
@@ -226,10 +350,10 @@ int hull_sc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_lo
             uint8_t *mask, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
             void *stream)
 {
-    (void)ws; (void)ws_bytes;
     if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low)) return HULL_EINVAL;
+    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
     hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, s);
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s);
     if (rc != HULL_OK) return rc;
     if (mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, mask, voxels(grid));
     return launch_status();
@@ -239,12 +363,12 @@ int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_l
              int mode, int nbr, int32_t *N, uint8_t *mask, uint32_t flags, hullmi_stats *stats,
              void *ws, size_t ws_bytes, void *stream)
 {
-    (void)ws; (void)ws_bytes;
     if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low) ||
         !msc_args_ok(n_t, mode, nbr))
         return HULL_EINVAL;
+    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
     hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, s);
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s);
     if (rc != HULL_OK) return rc;
     return run_msc_mask(grid, N, mask, n_t, mode, nbr, s);
 }
@@ -256,11 +380,13 @@ int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_hi
     if (!hist_ok(hist) || !grid_ok(grid) || !M || !std::isfinite(wepl_high) ||
         !sm_args_ok(frac_num, frac_den, mode, scope, nbr))
         return HULL_EINVAL;
-    if (mask && (!ws || ws_bytes < sm_ws_bytes(grid))) return HULL_ENOMEM;
+    const size_t cw = counts_ws_bytes(grid, hist->n);
+    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
     hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, s);
+    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, ws, s);
     if (rc != HULL_OK) return rc;
-    return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr, ws, s);
+    return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr,
+                       reinterpret_cast<char *>(ws) + cw, s);
 }
 
 int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
@@ -272,16 +398,17 @@ int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     if (msc_mask && !msc_args_ok(p->msc_n_t, p->msc_mode, p->nbr)) return HULL_EINVAL;
     if (sm_mask && !sm_args_ok(p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr))
         return HULL_EINVAL;
-    if (sm_mask && (!ws || ws_bytes < sm_ws_bytes(grid))) return HULL_ENOMEM;
+    const size_t cw = counts_ws_bytes(grid, hist->n);
+    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
     hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, s);
+    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, ws, s);
     if (rc != HULL_OK) return rc;
     if (sc_mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, sc_mask, voxels(grid));
     rc = launch_status();
     if (rc == HULL_OK) rc = run_msc_mask(grid, N, msc_mask, p->msc_n_t, p->msc_mode, p->nbr, s);
     if (rc == HULL_OK)
         rc = run_sm_mask(grid, M, sm_mask, p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope,
-                         p->nbr, ws, s);
+                         p->nbr, reinterpret_cast<char *>(ws) + cw, s);
     return rc;
 }
 

@@ -1,0 +1,66 @@
+// Slice-binned counting: the (history, z-slice) items of a batch are sorted by
+// (class, slice, length class); a persistent grid of workgroups takes
+// contiguous ranges of equal estimated work from that list and accumulates
+// each slice it meets in a 16-bit LDS copy, written out as a partial tile when
+// its range leaves the slice; a reduction then adds the partials into N or M.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hull_device.h"
+#include "hullmi.h"
+
+namespace hullmi {
+
+constexpr int kBinThreads = 256;        // classify / scatter block
+constexpr int kHistPerThread = 32;
+constexpr int kHistPerBlock = kBinThreads * kHistPerThread;
+constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic walk
+constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
+constexpr int kTileThreads = 512;       // workgroup of the LDS walk
+constexpr int kMaxTileVoxels = 65536;   // 16-bit counters: 128 KB of LDS
+constexpr int kItemsPerRange = 32768;   // a range holds at most 2x this many items
+constexpr int kWorkPerItem = 16;        // fixed cost of an item in visit units (set-up)
+constexpr int64_t kBatch = int64_t(1) << 24;   // histories per internal batch
+
+// meta word per history: valid | overflow | class | nslices | first slice
+constexpr uint32_t kMetaValid = 1u << 31;
+constexpr uint32_t kMetaOverflow = 1u << 25;
+constexpr uint32_t kMetaHigh = 1u << 24;
+
+// control words written on the device by the planning kernel
+enum : int { kCtlRanges = 0, kCtlItems = 1, kCtlOverflowStart = 2, kCtlOverflowCount = 3,
+             kCtlOverflowLow = 4, kCtlWords = 16 };
+
+struct BinWs {
+    int32_t *q;             // [B][6] quantised endpoints of the batch (one 24-byte record each)
+    uint32_t *meta;         // per history
+    uint32_t *lpack;        // per history: 4-bit length class per slice
+    uint32_t *blk;          // [nsub][nblk] counts, then offsets
+    uint32_t *sub_total;    // [nsub]
+    uint32_t *sub_start;    // [nsub + 1]
+    uint32_t *tile_start;   // [ntiles + 1]
+    uint32_t *range_start;  // [max_ranges + 1] item bounds of the ranges
+    uint32_t *range_coarse; // [max_ranges + 1] equal-work bounds before splitting
+    uint32_t *range_piece;  // [max_ranges] first final range of each coarse range
+    unsigned long long *wprefix;  // [nsub + 1] work prefix of the sub-bins
+    int32_t *ctl;           // kCtlWords
+    uint32_t *items;        // [B * kMaxSlicesPerLine] history of each (history, slice) item
+    uint32_t *partial;      // [max_slots][tile_words]
+    int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
+    int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;
+    int64_t B;
+};
+
+__global__ void k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_low,
+                               float e_high, int use_low, int use_high, int tile_ok, BinWs w,
+                               hullmi_stats *st);
+__global__ void k_bin_scan_blocks(BinWs w);
+__global__ void k_bin_plan(BinWs w);
+__global__ void k_bin_scatter(int64_t nb, BinWs w);
+__global__ void k_walk_tiles(BinWs w, int nx, int ny);
+__global__ void k_reduce_tiles(BinWs w, int plane, int *N, int *M, hullmi_stats *st);
+__global__ void k_walk_overflow(BinWs w, int nx, int ny, int nz, int *N, int *M, hullmi_stats *st);
+
+}  // namespace hullmi

@@ -1,0 +1,476 @@
+// Slice-binned counting kernels. A batch of histories goes through:
+//   classify : class, geometry, exact z-slice range of A_i, a length class per
+//              slice, per-block counts of the sub-bins (class, slice, length)
+//   scan     : per sub-bin offsets of every block
+//   plan     : sub-bin starts, slice (tile) starts, ranges of equal estimated
+//              work over the sorted item list
+//   scatter  : (history, slice) items in sub-bin order
+//   walk     : persistent workgroups; each range is cut at slice boundaries
+//              into segments, each accumulated in a 16-bit LDS copy of its
+//              slice and written to its own partial slot
+//   reduce   : the partial slots of every slice summed into N / M
+//   overflow : lines spanning many slices walked with global atomics
+// Counts are integers, so the result does not depend on any of this order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hull_binned.h"
+#include "hull_device.h"
+
+namespace hullmi {
+
+__device__ __forceinline__ void add_stats(hullmi_stats *st, int idx, unsigned long long v)
+{
+    if (v) atomicAdd(reinterpret_cast<unsigned long long *>(st) + idx, v);
+}
+
+// Block-wide sum (wave64, up to 1024 threads); the result is valid in thread 0.
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v, unsigned long long *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    return s;
+}
+
+// Number of entries of the non-decreasing array a[lo..hi) that are <= x.
+__device__ __forceinline__ int count_le(const uint32_t *a, int lo, int hi, uint32_t x)
+{
+    int l = lo, r = hi;
+    while (l < r) {
+        const int m = (l + r) >> 1;
+        if (a[m] <= x) l = m + 1; else r = m;
+    }
+    return l - lo;
+}
+
+// Partial slot of the segment that starts at item x: the number of range and
+// slice boundaries at or before x. Distinct non-empty segments get distinct
+// slots, at most ranges + slices of them.
+__device__ __forceinline__ int slot_of(const BinWs &w, int nranges, uint32_t x)
+{
+    return count_le(w.range_start, 1, nranges + 1, x) + count_le(w.tile_start, 1, w.ntiles, x);
+}
+
+// Approximate number of voxels of the line inside slice k (FP32, only used to
+// group lines of similar length), as a class in [0, nl).
+__device__ __forceinline__ int length_class(const int q[6], int nx, int ny, int nz, int k, int nl,
+                                            int lwidth)
+{
+    const float s = 1.0f / (float)kQ;
+    const float p[3] = {q[0] * s, q[1] * s, q[2] * s};
+    const float d[3] = {(q[3] - q[0]) * s, (q[4] - q[1]) * s, (q[5] - q[2]) * s};
+    const float n[3] = {(float)nx, (float)ny, (float)nz};
+    float tlo = -3.0e38f, thi = 3.0e38f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0f) {
+            const float r = __builtin_amdgcn_rcpf(d[a]);
+            const float t0 = (0.0f - p[a]) * r, t1 = (n[a] - p[a]) * r;
+            tlo = fmaxf(tlo, fminf(t0, t1));
+            thi = fminf(thi, fmaxf(t0, t1));
+        }
+    }
+    if (d[2] != 0.0f) {
+        const float r = __builtin_amdgcn_rcpf(d[2]);
+        const float t0 = ((float)k - p[2]) * r, t1 = ((float)(k + 1) - p[2]) * r;
+        tlo = fmaxf(tlo, fminf(t0, t1));
+        thi = fminf(thi, fmaxf(t0, t1));
+    }
+    const float len = (fabsf(d[0]) + fabsf(d[1])) * fmaxf(thi - tlo, 0.0f) + 1.0f;
+    const float c = fminf(len * __builtin_amdgcn_rcpf((float)lwidth), (float)(nl - 1));
+    return c > 0.0f ? (int)c : 0;
+}
+
+__global__ void __launch_bounds__(kBinThreads)
+k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_low, float e_high,
+               int use_low, int use_high, int tile_ok, BinWs w, hullmi_stats *st)
+{
+    __shared__ uint32_t lh[kMaxSubBins];
+    __shared__ unsigned long long red[16];
+    for (int b = threadIdx.x; b < w.nsub; b += blockDim.x) lh[b] = 0;
+    __syncthreads();
+    unsigned long long nl = 0, nh = 0, nsk = 0, nmi = 0;
+    const int64_t base = (int64_t)blockIdx.x * kHistPerBlock;
+    for (int r = 0; r < kHistPerThread; ++r) {
+        const int64_t j = base + (int64_t)r * kBinThreads + threadIdx.x;
+        if (j >= nb) break;
+        const int64_t i = h0 + j;
+        uint32_t meta = 0;
+        const float wv = h.wepl[i];
+        if (!isfinite(wv)) {
+            ++nsk;
+        } else {
+            const bool low = use_low && wv < e_low;
+            const bool high = use_high && wv > e_high;
+            if (low || high) {
+                const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
+                const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
+                const float a = h.angle_deg[i];
+                int q[6];
+                int stg = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) &&
+                           isfinite(yo) && isfinite(zo) && isfinite(a))
+                              ? kGeoOk
+                              : kGeoNonFinite;
+                if (stg == kGeoOk) {
+                    float c, s;
+                    deg_cos_sin(a, c, s);
+                    stg = quantize_point(c, s, xi, yi, zi, g, q[0], q[1], q[2]);
+                    if (stg == kGeoOk) stg = quantize_point(c, s, xo, yo, zo, g, q[3], q[4], q[5]);
+                    if (stg == kGeoOk && q[0] == q[3] && q[1] == q[4] && q[2] == q[5])
+                        stg = kGeoDegenerate;
+                }
+                if (stg != kGeoOk) {
+                    ++nsk;
+                } else {
+                    if (low) ++nl; else ++nh;
+                    int k0, k1;
+                    if (!line_z_range(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz, k0, k1)) {
+                        ++nmi;
+                    } else {
+                        const int cls = low ? 0 : 1;
+                        const int ns = k1 - k0 + 1;
+                        meta = kMetaValid | (cls ? kMetaHigh : 0u) | ((uint32_t)ns << 12) | (uint32_t)k0;
+                        if (!tile_ok || ns > kMaxSlicesPerLine) {
+                            meta |= kMetaOverflow;
+                            atomicAdd(&lh[w.nsub - 2 + cls], 1u);
+                        } else {
+                            uint32_t lp = 0;
+                            for (int k = k0; k <= k1; ++k) {
+                                const int lc = length_class(q, g.nx, g.ny, g.nz, k, w.nl, w.lwidth);
+                                lp |= (uint32_t)lc << (4 * (k - k0));
+                                atomicAdd(&lh[(cls * w.nz + k) * w.nl + lc], 1u);
+                            }
+                            w.lpack[j] = lp;
+                        }
+                        int2 *rec = reinterpret_cast<int2 *>(w.q + 6 * j);
+                        rec[0] = make_int2(q[0], q[1]);
+                        rec[1] = make_int2(q[2], q[3]);
+                        rec[2] = make_int2(q[4], q[5]);
+                    }
+                }
+            }
+        }
+        w.meta[j] = meta;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
+        w.blk[(int64_t)b * w.nblk + blockIdx.x] = lh[b];
+    if (st) {
+        unsigned long long v;
+        v = block_sum(nl, red);  if (threadIdx.x == 0) add_stats(st, 0, v);
+        v = block_sum(nh, red);  if (threadIdx.x == 0) add_stats(st, 1, v);
+        v = block_sum(nsk, red); if (threadIdx.x == 0) add_stats(st, 2, v);
+        v = block_sum(nmi, red); if (threadIdx.x == 0) add_stats(st, 3, v);
+    }
+}
+
+// One block per sub-bin: exclusive scan of its per-block counts, in place.
+__global__ void __launch_bounds__(256) k_bin_scan_blocks(BinWs w)
+{
+    __shared__ uint32_t part[256];
+    uint32_t *row = w.blk + (int64_t)blockIdx.x * w.nblk;
+    const int per = (w.nblk + 255) / 256;
+    const int b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int i = 0; i < per && b0 + i < w.nblk; ++i) s += row[b0 + i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int t = 0; t < 256; ++t) { const uint32_t v = part[t]; part[t] = acc; acc += v; }
+        w.sub_total[blockIdx.x] = acc;
+    }
+    __syncthreads();
+    uint32_t acc = part[threadIdx.x];
+    for (int i = 0; i < per && b0 + i < w.nblk; ++i) {
+        const uint32_t v = row[b0 + i];
+        row[b0 + i] = acc;
+        acc += v;
+    }
+}
+
+// Exclusive scan of get(0..n) into out[0..n) by one block (wave64 shuffles
+// and one LDS pass over the wave totals); returns the total in every thread.
+template <typename T, class Get>
+__device__ T block_exclusive_scan(int n, Get get, T *out, T *sh)
+{
+    const int nt = (int)blockDim.x;
+    const int per = (n + nt - 1) / nt;
+    const int b0 = threadIdx.x * per;
+    T s = 0;
+    for (int i = 0; i < per && b0 + i < n; ++i) s += get(b0 + i);
+    // inclusive scan within the wave
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T inc = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const T v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = 0;
+        for (int i = 0; i < (nt >> 6); ++i) { const T v = sh[i]; sh[i] = acc; acc += v; }
+        sh[nt >> 6] = acc;
+    }
+    __syncthreads();
+    T acc = sh[wid] + inc - s;
+    for (int i = 0; i < per && b0 + i < n; ++i) {
+        const T v = get(b0 + i);
+        out[b0 + i] = acc;
+        acc += v;
+    }
+    const T total = sh[nt >> 6];
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ unsigned long long item_work(const BinWs &w, int sub)
+{
+    const int lc = sub % w.nl;
+    return kWorkPerItem + (unsigned long long)lc * w.lwidth + w.lwidth / 2;
+}
+
+// Single block: sub-bin and slice starts, then the ranges: P0 = max(min_ranges,
+// ceil(I / kItemsPerRange)) ranges of equal estimated work, each split again
+// where it holds more than kItemsPerRange items, so that a range never adds
+// more than 2^15 to one 16-bit counter.
+__global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
+{
+    __shared__ unsigned long long shw[17];
+    __shared__ uint32_t shu[17];
+    const int nreg = w.ntiles * w.nl;
+    const uint32_t total = block_exclusive_scan<uint32_t>(
+        w.nsub, [&](int i) { return w.sub_total[i]; }, w.sub_start, shu);
+    if (threadIdx.x == 0) w.sub_start[w.nsub] = total;
+    const unsigned long long wtot = block_exclusive_scan<unsigned long long>(
+        nreg, [&](int i) { return (unsigned long long)w.sub_total[i] * item_work(w, i); },
+        w.wprefix, shw);
+    if (threadIdx.x == 0) w.wprefix[nreg] = wtot;
+    __syncthreads();
+    const uint32_t I = w.sub_start[nreg];
+    for (int t = threadIdx.x; t <= w.ntiles; t += blockDim.x) w.tile_start[t] = w.sub_start[t * w.nl];
+    uint32_t P0 = (I + kItemsPerRange - 1) / kItemsPerRange;
+    if (P0 < (uint32_t)w.min_ranges) P0 = w.min_ranges;
+    // coarse bounds: first item whose work prefix reaches r * wtot / P0
+    for (uint32_t r = threadIdx.x; r <= P0; r += blockDim.x) {
+        uint32_t item;
+        if (r == 0) item = 0;
+        else if (r == P0 || wtot == 0) item = I;
+        else {
+            const unsigned long long X = (unsigned long long)r * wtot / P0;
+            int l = 0, h = nreg;   // last sub-bin s with wprefix[s] <= X
+            while (l < h) {
+                const int m = (l + h + 1) >> 1;
+                if (w.wprefix[m] <= X) l = m; else h = m - 1;
+            }
+            const unsigned long long per = item_work(w, l);
+            unsigned long long k = (X - w.wprefix[l] + per - 1) / per;
+            if (k > w.sub_total[l]) k = w.sub_total[l];
+            item = min(w.sub_start[l] + (uint32_t)k, I);
+        }
+        w.range_coarse[r] = item;
+    }
+    __syncthreads();
+    // pieces per coarse range and their starts
+    auto pieces = [&](int r) {
+        const uint32_t cnt = w.range_coarse[r + 1] - w.range_coarse[r];
+        return cnt > (uint32_t)kItemsPerRange ? (cnt + kItemsPerRange - 1) / kItemsPerRange : 1u;
+    };
+    const uint32_t P = block_exclusive_scan<uint32_t>((int)P0, pieces, w.range_piece, shu);
+    for (uint32_t r = threadIdx.x; r < P0; r += blockDim.x) {
+        const uint32_t a = w.range_coarse[r], cnt = w.range_coarse[r + 1] - a;
+        const uint32_t np = pieces((int)r), o = w.range_piece[r];
+        for (uint32_t j = 0; j < np; ++j)
+            w.range_start[o + j] = a + (uint32_t)((unsigned long long)cnt * j / np);
+    }
+    if (threadIdx.x == 0) {
+        w.range_start[P] = I;
+        w.ctl[kCtlRanges] = (int32_t)P;
+        w.ctl[kCtlItems] = (int32_t)I;
+        w.ctl[kCtlOverflowStart] = (int32_t)w.sub_start[w.nsub - 2];
+        w.ctl[kCtlOverflowCount] = (int32_t)(w.sub_total[w.nsub - 2] + w.sub_total[w.nsub - 1]);
+        w.ctl[kCtlOverflowLow] = (int32_t)w.sub_total[w.nsub - 2];
+    }
+}
+
+__global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w)
+{
+    __shared__ uint32_t cur[kMaxSubBins];
+    for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
+        cur[b] = w.sub_start[b] + w.blk[(int64_t)b * w.nblk + blockIdx.x];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kHistPerBlock;
+    for (int r = 0; r < kHistPerThread; ++r) {
+        const int64_t j = base + (int64_t)r * kBinThreads + threadIdx.x;
+        if (j >= nb) break;
+        const uint32_t m = w.meta[j];
+        if (!(m & kMetaValid)) continue;
+        const int cls = (m & kMetaHigh) ? 1 : 0;
+        if (m & kMetaOverflow) {
+            const uint32_t p = atomicAdd(&cur[w.nsub - 2 + cls], 1u);
+            w.items[p] = (uint32_t)j;
+        } else {
+            const int k0 = (int)(m & 0xfffu), ns = (int)((m >> 12) & 0xfffu);
+            const uint32_t lp = w.lpack[j];
+            for (int k = k0; k < k0 + ns; ++k) {
+                const int lc = (int)((lp >> (4 * (k - k0))) & 0xfu);
+                const uint32_t p = atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u);
+                w.items[p] = (uint32_t)j;
+            }
+        }
+    }
+}
+
+// 16-bit counters packed in pairs into 32-bit LDS words; the walk hands over
+// the byte offset 2 * voxel of the counter.
+struct LdsAcc16 {
+    uint32_t *t;
+    __device__ __forceinline__ void operator()(int boff) const
+    {
+        const uint32_t b = (uint32_t)boff;
+        atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(t) + (b & ~3u)),
+                  1u + 65535u * ((b >> 1) & 1u));
+    }
+};
+
+// Persistent workgroups over the ranges; a range is cut at slice boundaries
+// into segments, each accumulated in the LDS copy of its slice and written to
+// its partial slot. The next item's endpoints are loaded while the current
+// line is walked.
+__global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, int ny)
+{
+    extern __shared__ uint32_t lds[];   // tile (tile_words), then 3 control words
+    uint32_t *tile = lds;
+    uint32_t *seg = lds + w.tile_words;
+    const int nranges = w.ctl[kCtlRanges];
+    LdsAcc16 acc{tile};
+    for (int r = blockIdx.x; r < nranges; r += gridDim.x) {
+        uint32_t x = w.range_start[r];
+        const uint32_t b = w.range_start[r + 1];
+        while (x < b) {
+            if (threadIdx.x == 0) {
+                const int t = count_le(w.tile_start, 0, w.ntiles, x) - 1;   // slice holding x
+                seg[0] = (uint32_t)t;
+                seg[1] = min(b, w.tile_start[t + 1]);
+                seg[2] = (uint32_t)slot_of(w, nranges, x);
+            }
+            for (int i = threadIdx.x; i < w.tile_words; i += blockDim.x) tile[i] = 0;
+            __syncthreads();
+            const int t = (int)seg[0];
+            const uint32_t y = seg[1], slot = seg[2];
+            const int k = t % w.nz;
+            // two-deep prefetch: the history index two items ahead and the
+            // endpoint record one item ahead are in flight during a walk
+            const uint32_t S = blockDim.x;
+            uint32_t it = x + threadIdx.x;
+            int2 c0 = make_int2(0, 0), c1 = c0, c2 = c0;
+            if (it < y) {
+                const int2 *r = reinterpret_cast<const int2 *>(w.q + 6 * (size_t)w.items[it]);
+                c0 = r[0]; c1 = r[1]; c2 = r[2];
+            }
+            uint32_t jn = it + S < y ? w.items[it + S] : 0u;
+            while (it < y) {
+                const int2 a0 = c0, a1 = c1, a2 = c2;
+                if (it + S < y) {
+                    const int2 *r = reinterpret_cast<const int2 *>(w.q + 6 * (size_t)jn);
+                    c0 = r[0]; c1 = r[1]; c2 = r[2];
+                }
+                jn = it + 2 * S < y ? w.items[it + 2 * S] : 0u;
+                walk_slice<2>(a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, nx, ny, k, acc);
+                it += S;
+            }
+            __syncthreads();
+            uint32_t *dst = w.partial + (int64_t)slot * w.tile_words;
+            for (int i = threadIdx.x; i < w.tile_words; i += blockDim.x) dst[i] = tile[i];
+            x = y;
+            __syncthreads();
+        }
+    }
+}
+
+// Adds the partial slots of every slice into N or M; the sum of what is added
+// is the number of voxel visits of the class.
+__global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N, int *M, hullmi_stats *st)
+{
+    __shared__ uint32_t slots[256];
+    __shared__ int nslots, more;
+    __shared__ unsigned long long red[16];
+    const int t = blockIdx.y;
+    const int cls = t / w.nz, k = t % w.nz;
+    const uint32_t ta = w.tile_start[t], tb = w.tile_start[t + 1];
+    if (ta == tb) return;   // uniform across the block
+    const int nranges = w.ctl[kCtlRanges];
+    const int wd = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t lo = 0, hi = 0;
+    // ranges overlapping [ta, tb), 256 at a time
+    int r = count_le(w.range_start, 0, nranges + 1, ta) - 1;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int n = 0;
+            while (n < 256 && r < nranges && w.range_start[r] < tb) {
+                const uint32_t a = max(w.range_start[r], ta), b = min(w.range_start[r + 1], tb);
+                if (a < b) slots[n++] = (uint32_t)slot_of(w, nranges, a);
+                ++r;
+            }
+            nslots = n;
+            more = (r < nranges && w.range_start[r] < tb) ? 1 : 0;
+        }
+        __syncthreads();
+        if (wd < w.tile_words)
+            for (int s = 0; s < nslots; ++s) {
+                const uint32_t v = w.partial[(int64_t)slots[s] * w.tile_words + wd];
+                lo += v & 0xffffu;
+                hi += v >> 16;
+            }
+        if (!more) break;   // r advances in thread 0 only
+    }
+    int *dst = cls ? M : N;
+    if (wd < w.tile_words) {
+        const int64_t v0 = (int64_t)k * plane + 2 * wd;
+        dst[v0] += (int)lo;
+        if (2 * wd + 1 < plane) dst[v0 + 1] += (int)hi;
+    }
+    if (st) {
+        const unsigned long long v = block_sum((unsigned long long)lo + hi, red);
+        if (threadIdx.x == 0) add_stats(st, 4 + cls, v);
+    }
+}
+
+struct GlobalAcc3 {
+    int *cnt;
+    __device__ __forceinline__ void operator()(int off) const { atomicAdd(cnt + off, 1); }
+};
+
+// Lines listed in the overflow bins, walked through the whole grid with global
+// atomics (grid-stride over a count known only on the device).
+__global__ void __launch_bounds__(256)
+k_walk_overflow(BinWs w, int nx, int ny, int nz, int *N, int *M, hullmi_stats *st)
+{
+    __shared__ unsigned long long red[16];
+    const int start = w.ctl[kCtlOverflowStart], count = w.ctl[kCtlOverflowCount];
+    const int nlow = w.ctl[kCtlOverflowLow];
+    unsigned long long vl = 0, vh = 0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        const int32_t *q = w.q + 6 * (size_t)w.items[start + t];
+        const bool high = t >= nlow;
+        GlobalAcc3 acc{high ? M : N};
+        const int v = walk_line(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, nz, acc);
+        if (high) vh += (unsigned long long)v; else vl += (unsigned long long)v;
+    }
+    if (st) {
+        unsigned long long v = block_sum(vl, red);
+        if (threadIdx.x == 0) add_stats(st, 4, v);
+        v = block_sum(vh, red);
+        if (threadIdx.x == 0) add_stats(st, 5, v);
+    }
+}
+
+}  // namespace hullmi

@@ -60,11 +60,6 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b)
 
 __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
 
-__device__ __forceinline__ int64_t sel3(int w, int64_t a, int64_t b, int64_t c)
-{
-    return w == 0 ? a : (w == 1 ? b : c);
-}
-
 // Walk state after set-up: the first voxel of A_i and, per axis, the next
 // crossing written as pairwise decision variables.
 //
@@ -187,6 +182,66 @@ __device__ __forceinline__ int walk_line(int qix, int qiy, int qiz, int qox, int
     const int64_t amax = max(w.Ax, max(w.Ay, w.Az));
     if (amax < (int64_t(1) << 19)) return walk_run<int32_t>(w, nx, ny, nz, acc);
     return walk_run<int64_t>(w, nx, ny, nz, acc);
+}
+
+}  // namespace hullmi
+
+namespace hullmi {
+
+// The part of A_i inside z-slice k, enumerated exactly. Inside one slice the
+// z index is constant, so once the first and the last voxel are known (the
+// last is the first voxel of the reversed line, since A_i does not depend on
+// the direction) the walk needs only the x/y decision variable: an axis steps
+// when it comes strictly first, both step when they tie (the line passes
+// through a voxel corner with both indices moving the same way; mixed
+// directions never tie, the sigma term breaks it). acc(S * (i + nx * j)) is
+// called once per voxel. The loop runs at most nx + ny times whatever happens.
+template <int S, typename T, class Acc>
+__device__ __forceinline__ void walk_slice_run(const WalkInit &a, int last, int nx, int ny, Acc &acc)
+{
+    T dxy = (T)a.dxy;
+    const T Kx = (T)(2048 * a.Ax), Ky = (T)(2048 * a.Ay);
+    const int ox = S * a.sx, oy = S * a.sy * nx;
+    int off = S * (a.cx + nx * a.cy);
+    const int maxit = nx + ny;
+    for (int it = 0; it < maxit; ++it) {
+        acc(off);
+        if (off == last) break;
+        const bool tie = dxy == 0;
+        const bool bx = dxy < 0;
+        dxy += bx ? Ky : -Kx;
+        off += bx ? ox : oy;
+        if (tie) {          // both axes step: add the x step on top of the y step
+            dxy += Ky;
+            off += ox;
+        }
+    }
+}
+
+template <int S, class Acc>
+__device__ __forceinline__ void walk_slice(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                           int nx, int ny, int k, Acc &acc)
+{
+    const int zs = k * kQ;
+    WalkInit a, b;
+    if (!walk_init(qix, qiy, qiz - zs, qox, qoy, qoz - zs, nx, ny, 1, a)) return;
+    if (!walk_init(qox, qoy, qoz - zs, qix, qiy, qiz - zs, nx, ny, 1, b)) return;
+    const int last = S * (b.cx + nx * b.cy);
+    if (max(a.Ax, a.Ay) < (int64_t(1) << 19)) walk_slice_run<S, int32_t>(a, last, nx, ny, acc);
+    else walk_slice_run<S, int64_t>(a, last, nx, ny, acc);
+}
+
+// z-index range of A_i over the whole grid: the first voxel of the line and of
+// the reversed line. Returns false when the line misses the grid.
+__device__ __forceinline__ bool line_z_range(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                             int nx, int ny, int nz, int &k0, int &k1)
+{
+    WalkInit a, b;
+    if (!walk_init(qix, qiy, qiz, qox, qoy, qoz, nx, ny, nz, a)) return false;
+    if (!walk_init(qox, qoy, qoz, qix, qiy, qiz, nx, ny, nz, b)) return false;
+    k0 = min(a.cz, b.cz);
+    k1 = max(a.cz, b.cz);
+    return true;
 }
 
 }  // namespace hullmi

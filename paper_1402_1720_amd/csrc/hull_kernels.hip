@@ -195,14 +195,33 @@ __global__ void k_msc_mask(const int *N, uint8_t *mask, int nx, int ny, int nz, 
     mask[v] = nv - lo < n_t;
 }
 
-// Largest value per segment (segments of seg_len voxels) with one atomicMax
-// per block and segment.
+// Block-wide maximum (wave64 shuffles, then LDS); valid in thread 0.
+__device__ __forceinline__ unsigned long long block_max(unsigned long long v)
+{
+    __shared__ unsigned long long sh[16];
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned long long)__shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long m = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = max(m, sh[i]);
+    return m;
+}
+
+// Largest M per segment (the whole volume, or one z-slice each):
+// blockIdx.y picks the segment, the blocks of a segment stride over it and
+// each issues one atomicMax.
 __global__ void __launch_bounds__(256)
 k_seg_max(const int *M, unsigned long long *out, int64_t V, int64_t seg_len)
 {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    atomicMax(out + v / seg_len, (unsigned long long)(unsigned)M[v]);
+    const int64_t base = (int64_t)blockIdx.y * seg_len;
+    const int64_t end = min(base + seg_len, V);
+    unsigned long long m = 0;
+    for (int64_t v = base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < end;
+         v += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (unsigned long long)(unsigned)M[v]);
+    m = block_max(m);
+    if (threadIdx.x == 0) atomicMax(out + blockIdx.y, m);
 }
 
 // Algorithm 3's maximum slope: per voxel the largest M(v) - M(w) over B(v)
@@ -213,23 +232,28 @@ k_seg_slope_argmax(const int *M, unsigned long long *out, int nx, int ny, int nz
                    int64_t seg_len)
 {
     const int64_t V = (int64_t)nx * ny * nz;
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    int i, j, k;
-    voxel_ijk(v, nx, ny, i, j, k);
-    const int64_t mv = M[v];
-    int64_t lo = mv;
-    if (i > 0) lo = min(lo, (int64_t)M[v - 1]);
-    if (i < nx - 1) lo = min(lo, (int64_t)M[v + 1]);
-    if (j > 0) lo = min(lo, (int64_t)M[v - nx]);
-    if (j < ny - 1) lo = min(lo, (int64_t)M[v + nx]);
-    if (nbr == HULL_NBR_SPATIAL6) {
-        const int64_t pl = (int64_t)nx * ny;
-        if (k > 0) lo = min(lo, (int64_t)M[v - pl]);
-        if (k < nz - 1) lo = min(lo, (int64_t)M[v + pl]);
+    const int64_t base = (int64_t)blockIdx.y * seg_len;
+    const int64_t end = min(base + seg_len, V);
+    const int64_t pl = (int64_t)nx * ny;
+    unsigned long long best = 0;
+    for (int64_t v = base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < end;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        voxel_ijk(v, nx, ny, i, j, k);
+        const int64_t mv = M[v];
+        int64_t lo = mv;
+        if (i > 0) lo = min(lo, (int64_t)M[v - 1]);
+        if (i < nx - 1) lo = min(lo, (int64_t)M[v + 1]);
+        if (j > 0) lo = min(lo, (int64_t)M[v - nx]);
+        if (j < ny - 1) lo = min(lo, (int64_t)M[v + nx]);
+        if (nbr == HULL_NBR_SPATIAL6) {
+            if (k > 0) lo = min(lo, (int64_t)M[v - pl]);
+            if (k < nz - 1) lo = min(lo, (int64_t)M[v + pl]);
+        }
+        best = max(best, ((unsigned long long)(mv - lo) << 32) | (unsigned long long)v);
     }
-    const unsigned long long key = ((unsigned long long)(mv - lo) << 32) | (unsigned long long)v;
-    atomicMax(out + v / seg_len, key);
+    best = block_max(best);
+    if (threadIdx.x == 0) atomicMax(out + blockIdx.y, best);
 }
 
 __global__ void k_sm_mask(const int *M, uint8_t *mask, int64_t V, int64_t seg_len, int mode,

@@ -208,6 +208,8 @@ def hull_sc(hist: Histories, grid, wepl_low: float, N: torch.Tensor,
             stats: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
     g = make_grid(grid)
     V = _voxels(g)
+    if ws is None:
+        ws = workspace(HULL_OP_SC, g, hist.n, hist.device)
     wp, wn = _ws(ws)
     rc = lib().hull_sc(ctypes.byref(hist.c), ctypes.byref(g), float(wepl_low),
                        _dev_ptr(N, torch.int32, V, "N", hist.device),
@@ -221,6 +223,8 @@ def hull_msc(hist: Histories, grid, wepl_low: float, n_t: int, mode: int, nbr: i
              stats: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
     g = make_grid(grid)
     V = _voxels(g)
+    if ws is None:
+        ws = workspace(HULL_OP_MSC, g, hist.n, hist.device)
     wp, wn = _ws(ws)
     rc = lib().hull_msc(ctypes.byref(hist.c), ctypes.byref(g), float(wepl_low), int(n_t), int(mode),
                         int(nbr), _dev_ptr(N, torch.int32, V, "N", hist.device),
@@ -235,7 +239,7 @@ def hull_sm(hist: Histories, grid, wepl_high: float, frac_num: int, frac_den: in
             ws: Optional[torch.Tensor] = None, stream=None):
     g = make_grid(grid)
     V = _voxels(g)
-    if ws is None and mask is not None:
+    if ws is None:
         ws = workspace(HULL_OP_SM, g, hist.n, hist.device)
     wp, wn = _ws(ws)
     rc = lib().hull_sm(ctypes.byref(hist.c), ctypes.byref(g), float(wepl_high), int(frac_num),

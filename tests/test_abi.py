@@ -40,8 +40,14 @@ def _grid(nx=8, ny=8, nz=4, d=1.0):
 
 def test_workspace_sizes():
     g = _grid()
-    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 100) == 0
-    assert H.hull_workspace_bytes(H.HULL_OP_ALL, g, 100) >= 8 * 4
+    assert H.hull_workspace_bytes(H.HULL_OP_COUNT_LINES, g, 100) == 0
+    sc = H.hull_workspace_bytes(H.HULL_OP_SC, g, 100)
+    assert sc > 100 * 24                       # quantised endpoints at least
+    assert H.hull_workspace_bytes(H.HULL_OP_MSC, g, 100) == sc
+    assert H.hull_workspace_bytes(H.HULL_OP_ALL, g, 100) >= sc + 8 * 4
+    # the batch caps the workspace: 2^24 histories at most
+    big = H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 24)
+    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 31 - 1) == big
     f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
     nb = 300 * 22 * 180
     assert H.hull_workspace_bytes(H.HULL_OP_FBP, g, 100, f) >= nb * 16
@@ -82,7 +88,7 @@ def test_sc_rejects_bad_arguments(case):
         thr = float("inf")
     elif case == "null_out":
         N = None
-    rc = L.hull_sc(ctypes.byref(h), ctypes.byref(g), thr, N, None, 0, None, None, 0, None)
+    rc = L.hull_sc(ctypes.byref(h), ctypes.byref(g), thr, N, None, 0, None, FAKE, 1 << 40, None)
     assert rc == H.HULL_EINVAL
 
 
@@ -90,7 +96,7 @@ def test_mode_and_threshold_checks():
     L = H.lib()
     h, g = _hist(), _grid()
     args = lambda nt, mode, nbr: (ctypes.byref(h), ctypes.byref(g), 1.0, nt, mode, nbr, FAKE, FAKE,
-                                  0, None, None, 0, None)
+                                  0, None, FAKE, 1 << 40, None)
     assert L.hull_msc(*args(0, 0, 0)) == H.HULL_EINVAL
     assert L.hull_msc(*args(5, 7, 0)) == H.HULL_EINVAL
     assert L.hull_msc(*args(5, 0, 3)) == H.HULL_EINVAL
@@ -103,6 +109,9 @@ def test_mode_and_threshold_checks():
     assert L.hull_sm(*smargs(3, 5, 0, 2, FAKE, 1 << 20)) == H.HULL_EINVAL
     # a mask needs the workspace
     assert L.hull_sm(*smargs(3, 5, 0, 0, None, 0)) == H.HULL_ENOMEM
+    assert L.hull_sm(*smargs(3, 5, 0, 0, FAKE, 64)) == H.HULL_ENOMEM
+    sc_args = (ctypes.byref(h), ctypes.byref(g), 1.0, FAKE, None, 0, None, FAKE, 64, None)
+    assert L.hull_sc(*sc_args) == H.HULL_ENOMEM
     f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
     assert L.hull_fbp(ctypes.byref(h), ctypes.byref(g), ctypes.byref(f), FAKE, None, FAKE, 16,
                       None) == H.HULL_ENOMEM

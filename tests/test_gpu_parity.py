@@ -311,3 +311,50 @@ def test_config3_subsample_bit_exact():
     rN, rM, rst = oracle.counts(h, G)
     gN, gM, gst = gpu_counts(h, spec.grid)
     assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
+
+
+# ---------------------------------------------------------------------------
+# paths of the slice-binned counting
+
+def _random_histories(rng, n, zspan, yspan=150.0):
+    return dict(x_in=np.full(n, -100.0, np.float32), y_in=rng.uniform(-yspan, yspan, n).astype(np.float32),
+                z_in=rng.uniform(-zspan, zspan, n).astype(np.float32),
+                x_out=np.full(n, 100.0, np.float32), y_out=rng.uniform(-yspan, yspan, n).astype(np.float32),
+                z_out=rng.uniform(-zspan, zspan, n).astype(np.float32),
+                angle_deg=rng.uniform(0, 360, n).astype(np.float32),
+                wepl=rng.choice(np.array([0.5, 3.0, 9.0], np.float32), n))
+
+
+def test_steep_lines_take_the_overflow_walk():
+    """Lines crossing more than eight slices are walked through the whole grid
+    with global atomics; shallow ones go through the LDS tiles. Same counts."""
+    rng = np.random.default_rng(17)
+    g = gen.Grid((48, 40, 64), (2.0, 2.0, 1.0))
+    h = _random_histories(rng, 60_000, 40.0, 60.0)
+    G = oracle.grid_of(g)
+    rN, rM, rst = oracle.counts(h, G)
+    gN, gM, gst = gpu_counts(h, g)
+    assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
+
+
+def test_grid_wider_than_a_tile():
+    """A 300x300 slice does not fit the 16-bit LDS tile: every line takes the
+    global-atomic walk."""
+    rng = np.random.default_rng(18)
+    g = gen.Grid((300, 300, 4), (0.7, 0.7, 5.0))
+    h = _random_histories(rng, 20_000, 8.0)
+    G = oracle.grid_of(g)
+    rN, rM, rst = oracle.counts(h, G)
+    gN, gM, gst = gpu_counts(h, g)
+    assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
+
+
+def test_two_internal_batches():
+    """More than 2^24 histories run as several internal batches."""
+    spec = gen.config_spec(1, n_hist=(1 << 24) + 4097)
+    h = gen.generate(spec)
+    G = oracle.grid_of(spec.grid)
+    say("two batches: oracle")
+    rN, rM, rst = oracle.counts(h, G)
+    gN, gM, gst = gpu_counts(h, spec.grid)
+    assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
