@@ -108,8 +108,9 @@ def main():
         return a.elapsed_time(b) / reps
 
     reps = max(3, args.steps)
-    # the walk kernel alone: with ACCUMULATE and no masks hull_all launches
-    # exactly one kernel (classify + geometry + walk + accumulate)
+    # the counting pass alone: with ACCUMULATE and no masks hull_all launches
+    # only the slice-binned counting kernels (classify, scan, plan, scatter,
+    # tile walk, reduce, overflow walk) on `stream`
     t_walk = timed(lambda: H.hull_all(hist, grid, params, N, M, flags=H.HULL_ACCUMULATE,
                                       ws=ws_all, stream=stream), reps)
     t_all = timed(lambda: H.hull_all(hist, grid, params, N, M, sc, msc, sm, ws=ws_all,
@@ -154,7 +155,11 @@ def main():
         "walk": {"ms": t_walk, "voxel_visits": visits, "visits_per_s": visits / (t_walk * 1e-3),
                  "n_low": st["n_low"], "n_high": st["n_high"],
                  "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
-        "roofline": {"bound": "alu", "kernel": "k_walk_histories", "achieved": achieved_tops,
+        "roofline": {"bound": "alu",
+                     "kernel": "counting pass: k_bin_classify + k_bin_scan_blocks + k_bin_plan + "
+                               "k_bin_scatter + k_walk_tiles + k_reduce_tiles + k_walk_overflow",
+                     "per_unit": "6 int32 lane-ops per voxel visit", "units": visits,
+                     "achieved": achieved_tops,
                      "peak": PEAK_INT_TOPS, "unit": "TOP/s", "frac": achieved_tops / PEAK_INT_TOPS,
                      "traffic": None},
         "cpu_baseline": None,

@@ -190,6 +190,7 @@ struct FbpWs {
     unsigned long long *sum;
     unsigned *cnt;
     float *q;
+    size_t qn;
     float2 *cs;
     size_t bytes;
 };
@@ -202,7 +203,9 @@ FbpWs fbp_ws_layout(const hullmi_fbp_params *p, void *base)
     size_t off = 0;
     w.sum = reinterpret_cast<unsigned long long *>(b + off); off += align_up(nb * 8);
     w.cnt = reinterpret_cast<unsigned *>(b + off);           off += align_up(nb * 4);
-    w.q = reinterpret_cast<float *>(b + off);                off += align_up(nb * 4);
+    w.q = reinterpret_cast<float *>(b + off);
+    w.qn = (size_t)p->n_angles * (p->nv + 4) * (p->nu + 4);   // padded filtered projections
+    off += align_up(w.qn * 4);
     w.cs = reinterpret_cast<float2 *>(b + off);              off += align_up((size_t)p->n_angles * 8);
     w.bytes = off;
     return w;
@@ -430,13 +433,26 @@ int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     const int64_t nb = (int64_t)p.nu * p.nv * p.n_angles;
     fill_u64(w.sum, 0ull, nb, s);
     fill_u32(w.cnt, 0u, nb, s);
-    if (hist->n > 0) k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
+    if (hist->n > 0) {
+        const size_t plane_lds = (size_t)p.nu * p.nv * 12;
+        if (plane_lds <= dev_props().max_lds) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_fbp_bin_lds),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane_lds);
+            const int64_t chunk = 32768;
+            k_fbp_bin_lds<<<(unsigned)((hist->n + chunk - 1) / chunk), kBlock, plane_lds, s>>>(
+                *hist, p, w.sum, w.cnt, chunk);
+        } else {
+            k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
+        }
+    }
     const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(double);
+    fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
     k_fbp_filter<<<(unsigned)(p.n_angles * p.nv), kBlock, lds, s>>>(w.sum, w.cnt, w.q, p);
     k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
     FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
                   grid->x0, grid->y0, grid->z0};
-    k_fbp_backproject<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(w.q, w.cs, p, gd, image, mask);
+    const int64_t ncol = (int64_t)grid->nx * grid->ny * ((grid->nz + 7) / 8);
+    k_fbp_backproject<<<blocks_for(ncol), kBlock, 0, s>>>(w.q, w.cs, p, gd, image, mask);
     return launch_status();
 }
 

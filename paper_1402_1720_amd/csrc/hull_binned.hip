@@ -336,7 +336,7 @@ struct LdsAcc16 {
     {
         const uint32_t b = (uint32_t)boff;
         atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(t) + (b & ~3u)),
-                  1u + 65535u * ((b >> 1) & 1u));
+                  1u + 65535u * __builtin_amdgcn_ubfe(b, 1u, 1u));
     }
 };
 
@@ -351,6 +351,8 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
     uint32_t *seg = lds + w.tile_words;
     const int nranges = w.ctl[kCtlRanges];
     LdsAcc16 acc{tile};
+    // LDS byte address of the tile (the low 32 bits of a local pointer)
+    const uint32_t tile_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)tile;
     for (int r = blockIdx.x; r < nranges; r += gridDim.x) {
         uint32_t x = w.range_start[r];
         const uint32_t b = w.range_start[r + 1];
@@ -383,7 +385,7 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
                     c0 = r[0]; c1 = r[1]; c2 = r[2];
                 }
                 jn = it + 2 * S < y ? w.items[it + 2 * S] : 0u;
-                walk_slice<2>(a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, nx, ny, k, acc);
+                walk_slice_tile16(a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, nx, ny, k, tile_base, acc);
                 it += S;
             }
             __syncthreads();

@@ -199,22 +199,91 @@ namespace hullmi {
 template <int S, typename T, class Acc>
 __device__ __forceinline__ void walk_slice_run(const WalkInit &a, int last, int nx, int ny, Acc &acc)
 {
-    T dxy = (T)a.dxy;
-    const T Kx = (T)(2048 * a.Ax), Ky = (T)(2048 * a.Ay);
-    const int ox = S * a.sx, oy = S * a.sy * nx;
+    T d = (T)a.dxy;
+    const T incx = (T)(2048 * a.Ay), incy = (T)(-2048 * a.Ax), incxy = incx + incy;
+    const int ox = S * a.sx, oy = S * a.sy * nx, oxy = ox + oy;
     int off = S * (a.cx + nx * a.cy);
+    // the iteration count is the same in every lane (a scalar register): the
+    // loop ends when no lane is live or after nx + ny rounds
     const int maxit = nx + ny;
+    bool live = true;
     for (int it = 0; it < maxit; ++it) {
-        acc(off);
-        if (off == last) break;
-        const bool tie = dxy == 0;
-        const bool bx = dxy < 0;
-        dxy += bx ? Ky : -Kx;
-        off += bx ? ox : oy;
-        if (tie) {          // both axes step: add the x step on top of the y step
-            dxy += Ky;
-            off += ox;
+        if (live) {
+            acc(off);
+            live = off != last;
+            const bool bx = d < 0, tie = d == 0;
+            d += bx ? incx : (tie ? incxy : incy);
+            off += bx ? ox : (tie ? oxy : oy);
         }
+        if (!__any(live)) break;
+    }
+}
+
+// The same loop for the 16-bit LDS tile written directly in gfx950 assembly
+// (the compiler keeps the loop guard and the any-lane test in vector
+// registers; here they are scalar): per step 12 VALU instructions and one
+// ds_add_u32. Lanes leave the exec mask when they have visited `last`; the
+// loop also ends after nx + ny rounds. Only LDS is touched: `base` is the LDS
+// byte address of the tile, `off` the byte offset 2 * voxel of the counter.
+__device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t last,
+                                                 int32_t incx, int32_t incy, int32_t ox,
+                                                 int32_t oy, uint32_t base, int32_t maxit)
+{
+    const int32_t incxy = incx + incy, oxy = ox + oy;
+    int32_t t0, t1, t2;
+    uint64_t save, sbx, stie;
+    int32_t it = maxit;
+    asm volatile(
+        "s_mov_b64 %[save], exec\n"
+        "1:\n"
+        // compares first: every SGPR a VALU writes is read at least three
+        // instructions later (gfx950 needs wait states between the two)
+        "v_cmp_gt_i32 %[sbx], 0, %[d]\n"
+        "v_cmp_eq_u32 %[stie], 0, %[d]\n"
+        "v_cmp_ne_u32 vcc, %[off], %[last]\n"
+        "v_and_b32 %[t0], -4, %[off]\n"
+        "v_bfe_u32 %[t1], %[off], 1, 1\n"
+        "v_add_u32 %[t0], %[base], %[t0]\n"
+        "v_cndmask_b32 %[t2], %[incy], %[incxy], %[stie]\n"
+        "v_cndmask_b32 %[t2], %[t2], %[incx], %[sbx]\n"
+        "v_add_u32 %[d], %[d], %[t2]\n"
+        "v_mad_u32_u24 %[t1], %[t1], %[k16], 1\n"
+        "ds_add_u32 %[t0], %[t1]\n"
+        "v_cndmask_b32 %[t2], %[oy], %[oxy], %[stie]\n"
+        "v_cndmask_b32 %[t2], %[t2], %[ox], %[sbx]\n"
+        "v_add_u32 %[off], %[off], %[t2]\n"
+        "s_and_b64 exec, exec, vcc\n"
+        "s_cbranch_execz 2f\n"
+        "s_sub_u32 %[it], %[it], 1\n"
+        "s_cmp_eq_u32 %[it], 0\n"
+        "s_cbranch_scc0 1b\n"
+        "2:\n"
+        "s_mov_b64 exec, %[save]\n"
+        : [d] "+v"(d), [off] "+v"(off), [it] "+s"(it), [t0] "=&v"(t0), [t1] "=&v"(t1),
+          [t2] "=&v"(t2), [save] "=&s"(save), [sbx] "=&s"(sbx), [stie] "=&s"(stie)
+        : [last] "v"(last), [incx] "v"(incx), [incy] "v"(incy), [incxy] "v"(incxy),
+          [ox] "v"(ox), [oy] "v"(oy), [oxy] "v"(oxy), [base] "v"(base), [k16] "s"(65535)
+        : "vcc", "scc", "memory");
+}
+
+// A_i inside slice k accumulated into a 16-bit LDS tile at LDS byte address
+// `base` (see walk_slice for the set-up; this variant uses walk_slice_lds16
+// for the common case of |D| < 2^19 and the C++ loop otherwise).
+template <class Acc>
+__device__ __forceinline__ void walk_slice_tile16(int qix, int qiy, int qiz, int qox, int qoy,
+                                                  int qoz, int nx, int ny, int k, uint32_t base,
+                                                  Acc &acc)
+{
+    const int zs = k * kQ;
+    WalkInit a, b;
+    if (!walk_init(qix, qiy, qiz - zs, qox, qoy, qoz - zs, nx, ny, 1, a)) return;
+    if (!walk_init(qox, qoy, qoz - zs, qix, qiy, qiz - zs, nx, ny, 1, b)) return;
+    const int last = 2 * (b.cx + nx * b.cy);
+    if (max(a.Ax, a.Ay) < (int64_t(1) << 19)) {
+        walk_slice_lds16((int32_t)a.dxy, 2 * (a.cx + nx * a.cy), last, (int32_t)(2048 * a.Ay),
+                         (int32_t)(-2048 * a.Ax), 2 * a.sx, 2 * a.sy * nx, base, nx + ny);
+    } else {
+        walk_slice_run<2, int64_t>(a, last, nx, ny, acc);
     }
 }
 

@@ -274,37 +274,111 @@ __global__ void k_sm_mask(const int *M, uint8_t *mask, int64_t V, int64_t seg_le
 // ---------------------------------------------------------------------------
 // FDK hull
 
-// Bin each history where its line crosses x = 0; WEPL sums in fixed point
-// (2^-16 mm) so the result does not depend on the order of the atomics.
-__global__ void __launch_bounds__(256)
-k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt)
+// Where a history's line crosses x = 0, decided in FP32: gantry angle bin k,
+// detector bin (iu, iv) and the WEPL in fixed point (2^-16 mm). False when the
+// history is not binned.
+__device__ __forceinline__ bool fbp_locate(const hullmi_histories &h, int64_t i, const FbpDev &p,
+                                           int &k, int &iu, int &iv, long long &fx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= h.n) return;
     const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
     const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
     const float a = h.angle_deg[i], w = h.wepl[i];
     if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
           isfinite(zo) && isfinite(a) && isfinite(w)))
-        return;
-    if (!(fabsf(w) < 65536.0f)) return;
+        return false;
+    if (!(fabsf(w) < 65536.0f)) return false;
     const float ddx = xo - xi;
-    if (ddx == 0.0f) return;
+    if (ddx == 0.0f) return false;
     const float r = (0.0f - xi) / ddx;
     const float u = yi + r * (yo - yi);
     const float v = zi + r * (zo - zi);
     const float fa = (a - p.angle0) * p.rda;
     const float fu = (u - p.u0) * p.rdu;
     const float fv = (v - p.v0) * p.rdv;
-    if (!(fabsf(fa) < 1.0e9f)) return;
-    if (!(fu >= 0.0f && fu < (float)p.nu && fv >= 0.0f && fv < (float)p.nv)) return;
-    long long k = (long long)rintf(fa) % p.n_angles;
-    if (k < 0) k += p.n_angles;
-    const int iu = (int)floorf(fu), iv = (int)floorf(fv);
+    if (!(fabsf(fa) < 1.0e9f)) return false;
+    if (!(fu >= 0.0f && fu < (float)p.nu && fv >= 0.0f && fv < (float)p.nv)) return false;
+    long long kk = (long long)rintf(fa) % p.n_angles;
+    if (kk < 0) kk += p.n_angles;
+    k = (int)kk;
+    iu = (int)floorf(fu);
+    iv = (int)floorf(fv);
+    fx = llrint((double)w * 65536.0);
+    return true;
+}
+
+// Angle bin of a history from its angle alone (-1 when it cannot be binned).
+__device__ __forceinline__ int fbp_angle_bin(float a, const FbpDev &p)
+{
+    if (!isfinite(a)) return -1;
+    const float fa = (a - p.angle0) * p.rda;
+    if (!(fabsf(fa) < 1.0e9f)) return -1;
+    long long kk = (long long)rintf(fa) % p.n_angles;
+    if (kk < 0) kk += p.n_angles;
+    return (int)kk;
+}
+
+// Bin each history; WEPL sums in fixed point so the result does not depend
+// on the order of the atomics. Used when a detector plane does not fit LDS.
+__global__ void __launch_bounds__(256)
+k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h.n) return;
+    int k, iu, iv;
+    long long fx;
+    if (!fbp_locate(h, i, p, k, iu, iv, fx)) return;
     const int64_t b = ((int64_t)k * p.nv + iv) * p.nu + iu;
-    const long long fx = llrint((double)w * 65536.0);
     atomicAdd(sum + b, (unsigned long long)fx);
     atomicAdd(cnt + b, 1u);
+}
+
+// The same binning for a chunk of consecutive histories per block: the chunk's
+// first angle bin (histories arrive angle by angle) is accumulated in an LDS
+// copy of its detector plane and added to the global sums once; histories of
+// other angle bins in the chunk go straight to the global sums. Same fixed
+// point, so the sums are identical to k_fbp_bin's.
+__global__ void __launch_bounds__(256)
+k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt, int64_t chunk)
+{
+    extern __shared__ unsigned long long lsum[];   // plane sums, then plane counts (u32)
+    const int plane = p.nu * p.nv;
+    unsigned *lcnt = reinterpret_cast<unsigned *>(lsum + plane);
+    __shared__ int kref;
+    const int64_t base = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(base + chunk, h.n);
+    if (threadIdx.x == 0) kref = 0x7fffffff;
+    for (int b = threadIdx.x; b < plane; b += blockDim.x) { lsum[b] = 0ull; lcnt[b] = 0u; }
+    __syncthreads();
+    // the smallest angle bin of the chunk's first 256 histories
+    if (base + threadIdx.x < end) {
+        const int k = fbp_angle_bin(h.angle_deg[base + threadIdx.x], p);
+        if (k >= 0) atomicMin(&kref, k);
+    }
+    __syncthreads();
+    const int kr = kref;
+    for (int64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+        int k, iu, iv;
+        long long fx;
+        if (!fbp_locate(h, i, p, k, iu, iv, fx)) continue;
+        const int pb = iv * p.nu + iu;
+        if (k == kr) {
+            atomicAdd(&lsum[pb], (unsigned long long)fx);
+            atomicAdd(&lcnt[pb], 1u);
+        } else {
+            const int64_t b = (int64_t)k * plane + pb;
+            atomicAdd(sum + b, (unsigned long long)fx);
+            atomicAdd(cnt + b, 1u);
+        }
+    }
+    __syncthreads();
+    if (kr == 0x7fffffff) return;
+    for (int b = threadIdx.x; b < plane; b += blockDim.x) {
+        const unsigned c = lcnt[b];
+        if (c) {
+            atomicAdd(sum + (int64_t)kr * plane + b, lsum[b]);
+            atomicAdd(cnt + (int64_t)kr * plane + b, c);
+        }
+    }
 }
 
 // One block per detector row: bin means, cosine pre-weight, then the
@@ -334,11 +408,14 @@ k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDe
         ker[m] = -2.0 / (pi * pi * du * du * (4.0 * n * n - 1.0));
     }
     __syncthreads();
+    // padded output: [n_angles][nv + 4][nu + 4], two zero bins on every side
+    const int64_t k = r / p.nv;
+    float *qr = q + (k * (p.nv + 4) + (iv + 2)) * (int64_t)(nu + 4) + 2;
     for (int iu = threadIdx.x; iu < nu; iu += blockDim.x) {
         double acc = 0.0;
         const double *kr = ker + iu + nu - 1;
         for (int j = 0; j < nu; ++j) acc += kr[-j] * row[j];
-        q[r * nu + iu] = (float)(du * acc);
+        qr[iu] = (float)(du * acc);
     }
 }
 
@@ -350,54 +427,68 @@ __global__ void k_fbp_trig(float2 *cs, FbpDev p)
     cs[k] = make_float2((float)cos(th), (float)sin(th));
 }
 
-// FDK backprojection, one voxel per lane, all angles; threshold fused.
+// FDK backprojection. One lane per (x, y) column and group of kFbpZ slices:
+// per angle the rotation, the magnification U and the u interpolation are
+// computed once and reused for every slice of the group. The filtered
+// projections carry two zero bins on every side, so an index clamped into
+// that border samples zeros. Threshold fused.
+constexpr int kFbpZ = 8;
+
 __global__ void __launch_bounds__(256)
 k_fbp_backproject(const float *q, const float2 *cs, FbpDev p, FbpGridDev g, float *image,
                   uint8_t *mask)
 {
-    const int64_t V = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    int i, j, k;
-    voxel_ijk(v, g.nx, g.ny, i, j, k);
+    const int ngz = (g.nz + kFbpZ - 1) / kFbpZ;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)g.nx * g.ny * ngz) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int kz0 = (int)(t / ((int64_t)g.nx * g.ny)) * kFbpZ;
+    const int nzg = min(kFbpZ, g.nz - kz0);
     const float xo = g.x0 + ((float)i + 0.5f) * g.dx;
     const float yo = g.y0 + ((float)j + 0.5f) * g.dy;
-    const float zo = g.z0 + ((float)k + 0.5f) * g.dz;
-    const float D = p.src_dist, rD = 1.0f / p.src_dist;
-    const int nu = p.nu, nv = p.nv;
-    float f = 0.0f;
+    float zo[kFbpZ], f[kFbpZ];
+#pragma unroll
+    for (int z = 0; z < kFbpZ; ++z) {
+        zo[z] = g.z0 + ((float)(kz0 + z) + 0.5f) * g.dz;
+        f[z] = 0.0f;
+    }
+    const float D = p.src_dist, rD = __builtin_amdgcn_rcpf(p.src_dist);
+    const int nu = p.nu, nv = p.nv, pu = nu + 4;
+    const int64_t pa = (int64_t)(nv + 4) * pu;
     for (int a = 0; a < p.n_angles; ++a) {
-        const float2 t = cs[a];
-        const float xl = t.x * xo - t.y * yo;
-        const float yl = t.y * xo + t.x * yo;
+        const float2 c = cs[a];
+        const float xl = c.x * xo - c.y * yo;
+        const float yl = c.y * xo + c.x * yo;
         const float U = (D + xl) * rD;
         if (!(U > 0.0f)) continue;   // voxel at or behind the source plane
-        const float iU = 1.0f / U;
+        const float iU = __builtin_amdgcn_rcpf(U);
+        const float w2 = iU * iU;
         const float fu = (yl * iU - p.u0) * p.rdu - 0.5f;
-        const float fv = (zo * iU - p.v0) * p.rdv - 0.5f;
-        if (!(fabsf(fu) < 1.0e8f && fabsf(fv) < 1.0e8f)) continue;
-        const float fu0 = floorf(fu), fv0 = floorf(fv);
-        const float au = fu - fu0, av = fv - fv0;
-        const int iu0 = (int)fu0, iv0 = (int)fv0;
-        const float *qa = q + (int64_t)a * nv * nu;
-        float val = 0.0f;
-        if (iv0 >= 0 && iv0 < nv) {
-            const float *qr = qa + (int64_t)iv0 * nu;
-            const float l = (iu0 >= 0 && iu0 < nu) ? qr[iu0] : 0.0f;
-            const float r = (iu0 + 1 >= 0 && iu0 + 1 < nu) ? qr[iu0 + 1] : 0.0f;
-            val += (1.0f - av) * ((1.0f - au) * l + au * r);
+        const float fu0 = floorf(fu);
+        const float au = fu - fu0;
+        const int iu0 = min(max((int)fmaxf(fminf(fu0, 1.0e8f), -1.0e8f), -2), nu);
+        const float *qa = q + (int64_t)a * pa + (iu0 + 2);
+        const float fvs = iU * p.rdv;
+#pragma unroll
+        for (int z = 0; z < kFbpZ; ++z) {
+            const float fv = zo[z] * fvs - p.v0 * p.rdv - 0.5f;
+            const float fv0 = floorf(fv);
+            const float av = fv - fv0;
+            const int iv0 = min(max((int)fmaxf(fminf(fv0, 1.0e8f), -1.0e8f), -2), nv);
+            const float *q0 = qa + (int64_t)(iv0 + 2) * pu;
+            const float l0 = q0[0], r0 = q0[1], l1 = q0[pu], r1 = q0[pu + 1];
+            const float top = l0 + au * (r0 - l0);
+            const float bot = l1 + au * (r1 - l1);
+            f[z] += (top + av * (bot - top)) * w2;
         }
-        if (iv0 + 1 >= 0 && iv0 + 1 < nv) {
-            const float *qr = qa + (int64_t)(iv0 + 1) * nu;
-            const float l = (iu0 >= 0 && iu0 < nu) ? qr[iu0] : 0.0f;
-            const float r = (iu0 + 1 >= 0 && iu0 + 1 < nu) ? qr[iu0 + 1] : 0.0f;
-            val += av * ((1.0f - au) * l + au * r);
-        }
-        f += val * iU * iU;
     }
-    f *= p.half_dth;
-    image[v] = f;
-    if (mask) mask[v] = f >= p.threshold;
+    for (int z = 0; z < nzg; ++z) {
+        const float v = f[z] * p.half_dth;
+        const int64_t vox = ((int64_t)(kz0 + z) * g.ny + j) * g.nx + i;
+        image[vox] = v;
+        if (mask) mask[vox] = v >= p.threshold;
+    }
 }
 
 }  // namespace hullmi
