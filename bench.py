@@ -33,6 +33,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "counting_pass_traffic_200x200x32_1e7.md")
+
+
+def measured_traffic():
+    """HBM bytes of one counting pass from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the counting kernels have changed since it was
+    taken (their sources no longer hash to the recorded value)."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(TRAFFIC_PROFILE):
+            k, sep, v = line.partition(":")
+            if sep and k.strip() in ("traffic_bytes_per_pass", "kernel_sources",
+                                     "kernel_sources_sha256"):
+                fields[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for f in fields["kernel_sources"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != fields["kernel_sources_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_pass"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,6 +65,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, run one 256 MiB device-to-device copy: the "
+                         "known-size kernel that scales hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hull path is measured "
@@ -72,10 +100,18 @@ def main():
     ws_fbp = H.workspace(H.HULL_OP_FBP, grid, n, dev, fbp)
     stats = torch.zeros(6, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream(device=dev)   # default priority, like every stream here
+    fork, join = torch.cuda.Event(), torch.cuda.Event()
 
     def step():
+        # the FDK hull and the counting pass are independent: FDK runs on a
+        # second stream and the step ends when both are done
+        fork.record(stream)
+        side.wait_event(fork)
+        H.hull_fbp(hist, grid, fbp, image, fmask, ws=ws_fbp, stream=side)
         H.hull_all(hist, grid, params, N, M, sc, msc, sm, stats=stats, ws=ws_all, stream=stream)
-        H.hull_fbp(hist, grid, fbp, image, fmask, ws=ws_fbp, stream=stream)
+        join.record(side)
+        stream.wait_event(join)
 
     for _ in range(args.warmup):
         step()
@@ -93,6 +129,12 @@ def main():
     wall = time.perf_counter() - wall0
     per_step = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
     ms_step = float(evs[0].elapsed_time(evs[-1]) / args.steps)
+    if args.copy_probe:
+        src = torch.ones(1 << 26, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     st = H.stats_dict(stats)
     visits = st["n_visits_low"] + st["n_visits_high"]
 
@@ -161,7 +203,7 @@ def main():
                      "per_unit": "6 int32 lane-ops per voxel visit", "units": visits,
                      "achieved": achieved_tops,
                      "peak": PEAK_INT_TOPS, "unit": "TOP/s", "frac": achieved_tops / PEAK_INT_TOPS,
-                     "traffic": None},
+                     "traffic": measured_traffic()},
         "cpu_baseline": None,
     }
 
