@@ -62,6 +62,15 @@ class OrStats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class OrParams(ctypes.Structure):
+    """Thresholds and modes of the one-pass call (the GPU library's
+    ``hullmi_params`` layout)."""
+    _fields_ = [("wepl_low", ctypes.c_float), ("wepl_high", ctypes.c_float),
+                ("msc_n_t", ctypes.c_int32), ("msc_mode", ctypes.c_int32),
+                ("sm_frac_num", ctypes.c_int32), ("sm_frac_den", ctypes.c_int32),
+                ("sm_mode", ctypes.c_int32), ("sm_scope", ctypes.c_int32), ("nbr", ctypes.c_int32)]
+
+
 class OrFbpParams(ctypes.Structure):
     _fields_ = [("src_dist_mm", ctypes.c_float), ("du_mm", ctypes.c_float),
                 ("dv_mm", ctypes.c_float), ("u0_mm", ctypes.c_float), ("v0_mm", ctypes.c_float),
@@ -96,6 +105,13 @@ def _lib():
             "or_fbp_filter": ([P, P], None),
             "or_fbp_backproject": ([P, P, P, P], None),
             "or_fbp": ([P, P, P, P, P, P], i64),
+            "oracle_hull_sc": ([P, P, ctypes.c_float, P, P, P], ctypes.c_int),
+            "oracle_hull_msc": ([P, P, ctypes.c_float, i32, ctypes.c_int, ctypes.c_int, P, P, P],
+                                ctypes.c_int),
+            "oracle_hull_sm": ([P, P, ctypes.c_float, i32, i32, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, P, P, P], ctypes.c_int),
+            "oracle_hull_all": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
+            "oracle_hull_fbp": ([P, P, P, P, P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -265,3 +281,69 @@ def fbp(hist, grid: OrGrid, p: OrFbpParams):
     used = _lib().or_fbp(ctypes.byref(hv.c), ctypes.byref(grid), ctypes.byref(p), _ptr(proj),
                          _ptr(img), _ptr(mask))
     return img, mask, proj, int(used)
+
+
+# ---------------------------------------------------------------------------
+# whole-call mirrors of the GPU library's per-scan calls (host arrays)
+
+def _vox(grid: OrGrid) -> int:
+    return int(grid.nx) * int(grid.ny) * int(grid.nz)
+
+
+def hull_sc(hist, grid: OrGrid, wepl_low: float = 1.0):
+    """(N, SC mask, stats)."""
+    hv = _HistView(hist)
+    V = _vox(grid)
+    N, mask, st = np.empty(V, np.int32), np.empty(V, np.uint8), OrStats()
+    if _lib().oracle_hull_sc(ctypes.byref(hv.c), ctypes.byref(grid), float(wepl_low), _ptr(N),
+                             _ptr(mask), ctypes.byref(st)) != 0:
+        raise ValueError("oracle_hull_sc rejected its arguments")
+    return N, mask, st.as_dict()
+
+
+def hull_msc(hist, grid: OrGrid, wepl_low: float, n_t: int, mode: int, nbr: int):
+    """(N, MSC mask, stats)."""
+    hv = _HistView(hist)
+    V = _vox(grid)
+    N, mask, st = np.empty(V, np.int32), np.empty(V, np.uint8), OrStats()
+    if _lib().oracle_hull_msc(ctypes.byref(hv.c), ctypes.byref(grid), float(wepl_low), int(n_t),
+                              int(mode), int(nbr), _ptr(N), _ptr(mask), ctypes.byref(st)) != 0:
+        raise ValueError("oracle_hull_msc rejected its arguments")
+    return N, mask, st.as_dict()
+
+
+def hull_sm(hist, grid: OrGrid, wepl_high: float, num: int, den: int, mode: int, scope: int,
+            nbr: int):
+    """(M, SM mask, stats)."""
+    hv = _HistView(hist)
+    V = _vox(grid)
+    M, mask, st = np.empty(V, np.int32), np.empty(V, np.uint8), OrStats()
+    if _lib().oracle_hull_sm(ctypes.byref(hv.c), ctypes.byref(grid), float(wepl_high), int(num),
+                             int(den), int(mode), int(scope), int(nbr), _ptr(M), _ptr(mask),
+                             ctypes.byref(st)) != 0:
+        raise ValueError("oracle_hull_sm rejected its arguments")
+    return M, mask, st.as_dict()
+
+
+def hull_all(hist, grid: OrGrid, p: OrParams):
+    """(N, M, SC mask, MSC mask, SM mask, stats)."""
+    hv = _HistView(hist)
+    V = _vox(grid)
+    N, M = np.empty(V, np.int32), np.empty(V, np.int32)
+    m1, m2, m3 = (np.empty(V, np.uint8) for _ in range(3))
+    st = OrStats()
+    if _lib().oracle_hull_all(ctypes.byref(hv.c), ctypes.byref(grid), ctypes.byref(p), _ptr(N),
+                              _ptr(M), _ptr(m1), _ptr(m2), _ptr(m3), ctypes.byref(st)) != 0:
+        raise ValueError("oracle_hull_all rejected its arguments")
+    return N, M, m1, m2, m3, st.as_dict()
+
+
+def hull_fbp(hist, grid: OrGrid, p: OrFbpParams):
+    """(image FP64, mask)."""
+    hv = _HistView(hist)
+    V = _vox(grid)
+    img, mask = np.empty(V, np.float64), np.empty(V, np.uint8)
+    if _lib().oracle_hull_fbp(ctypes.byref(hv.c), ctypes.byref(grid), ctypes.byref(p), _ptr(img),
+                              _ptr(mask)) != 0:
+        raise ValueError("oracle_hull_fbp rejected its arguments")
+    return img, mask

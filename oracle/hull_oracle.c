@@ -558,3 +558,88 @@ void or_quantize_all(const or_hist *h, const or_grid *g, int32_t *status, int32_
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < h->n; ++i) status[i] = or_quantize(h, g, i, qin + 3 * i, qout + 3 * i);
 }
+
+/* ------------------------------------------------------------------------
+ * Whole-call mirrors of the GPU library's per-scan calls: the same argument
+ * layouts (grid, histories, stats, parameters, FDK geometry) with host
+ * pointers and no stream or workspace. Counts are overwritten; masks, stats
+ * and the FDK mask may be NULL. The FDK image is FP64 here. Return 0, or 1
+ * when a required pointer is missing. */
+
+typedef struct {
+    float wepl_low, wepl_high;
+    int32_t msc_n_t, msc_mode;
+    int32_t sm_frac_num, sm_frac_den, sm_mode, sm_scope;
+    int32_t nbr;
+} or_params;
+
+static void or_stats_out(or_stats *dst, const or_stats *src)
+{
+    if (dst) *dst = *src;
+}
+
+int oracle_hull_sc(const or_hist *h, const or_grid *g, float wepl_low, int32_t *N, uint8_t *mask,
+                   or_stats *st)
+{
+    if (!h || !g || !N) return 1;
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    or_stats s;
+    memset(N, 0, (size_t)V * sizeof(int32_t));
+    or_counts(h, g, wepl_low, 0.0f, N, NULL, &s);
+    if (mask) or_sc(N, V, mask);
+    or_stats_out(st, &s);
+    return 0;
+}
+
+int oracle_hull_msc(const or_hist *h, const or_grid *g, float wepl_low, int32_t n_t, int mode,
+                    int nbr, int32_t *N, uint8_t *mask, or_stats *st)
+{
+    if (!h || !g || !N) return 1;
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    or_stats s;
+    memset(N, 0, (size_t)V * sizeof(int32_t));
+    or_counts(h, g, wepl_low, 0.0f, N, NULL, &s);
+    if (mask && or_msc(N, g, n_t, mode, nbr, mask) != 0) return 1;
+    or_stats_out(st, &s);
+    return 0;
+}
+
+int oracle_hull_sm(const or_hist *h, const or_grid *g, float wepl_high, int32_t num, int32_t den,
+                   int mode, int scope, int nbr, int32_t *M, uint8_t *mask, or_stats *st)
+{
+    if (!h || !g || !M) return 1;
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    or_stats s;
+    memset(M, 0, (size_t)V * sizeof(int32_t));
+    or_counts(h, g, 0.0f, wepl_high, NULL, M, &s);
+    if (mask && or_sm(M, g, num, den, mode, scope, nbr, mask, NULL) != 0) return 1;
+    or_stats_out(st, &s);
+    return 0;
+}
+
+int oracle_hull_all(const or_hist *h, const or_grid *g, const or_params *p, int32_t *N,
+                    int32_t *M, uint8_t *sc_mask, uint8_t *msc_mask, uint8_t *sm_mask,
+                    or_stats *st)
+{
+    if (!h || !g || !p || !N || !M) return 1;
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    or_stats s;
+    memset(N, 0, (size_t)V * sizeof(int32_t));
+    memset(M, 0, (size_t)V * sizeof(int32_t));
+    or_counts(h, g, p->wepl_low, p->wepl_high, N, M, &s);
+    if (sc_mask) or_sc(N, V, sc_mask);
+    if (msc_mask && or_msc(N, g, p->msc_n_t, p->msc_mode, p->nbr, msc_mask) != 0) return 1;
+    if (sm_mask && or_sm(M, g, p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr,
+                         sm_mask, NULL) != 0)
+        return 1;
+    or_stats_out(st, &s);
+    return 0;
+}
+
+int oracle_hull_fbp(const or_hist *h, const or_grid *g, const or_fbp_params *p, double *image,
+                    uint8_t *mask)
+{
+    if (!h || !g || !p || !image) return 1;
+    or_fbp(h, g, p, NULL, image, mask);
+    return 0;
+}
