@@ -58,6 +58,166 @@ def measured_traffic():
         return None
 
 
+def _timed_on(torch, stream, fn, reps):
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_batch(torch, gen, H, dev, reps=5):
+    """16 scans of uneven size on four grids (log-uniform 1e5..5e7 histories,
+    ellipsoids jittered +-15%, sigma U[1, 5] mm), each the one-pass SC + MSC +
+    SM call: one autotuned, graph-captured plan against the same 16 calls made
+    one after another on one stream."""
+    specs = gen.batch_specs()
+    params = H.make_params()
+    jobs, keep, total = [], [], 0
+    for sp in specs:
+        h = gen.generate(sp)
+        hist = H.Histories.from_numpy(h, dev)
+        del h
+        V = sp.grid.voxels
+        outs = dict(N=torch.zeros(V, dtype=torch.int32, device=dev),
+                    M=torch.zeros(V, dtype=torch.int32, device=dev),
+                    sc_mask=torch.zeros(V, dtype=torch.uint8, device=dev),
+                    msc_mask=torch.zeros(V, dtype=torch.uint8, device=dev),
+                    sm_mask=torch.zeros(V, dtype=torch.uint8, device=dev))
+        jobs.append(H.make_job(H.HULL_OP_ALL, hist, sp.grid, params, **outs))
+        keep.append((hist, outs, sp))
+        total += sp.n_hist
+    stream = torch.cuda.current_stream()
+    ws_bytes = max(H.hull_workspace_bytes(H.HULL_OP_ALL, sp.grid, sp.n_hist) for sp in specs)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+
+    def sequential():
+        for hist, o, sp in keep:
+            H.hull_all(hist, sp.grid, params, o["N"], o["M"], o["sc_mask"], o["msc_mask"],
+                       o["sm_mask"], ws=ws, stream=stream)
+
+    t_seq = _timed_on(torch, stream, sequential, reps)
+    t0 = time.perf_counter()
+    plan = H.BatchPlan(jobs, keep=keep)
+    t_plan_s = time.perf_counter() - t0
+    t_batch = _timed_on(torch, stream, lambda: plan.launch(stream), reps)
+    tune = plan.tuning
+    plan.close()
+    return {"workload": "16 scans, log-uniform 1e5..5e7 histories on 64x64x16 / 128x128x32 / "
+                        "200x200x32 / 256x256x64 grids, SC+MSC+SM one pass each",
+            "histories": total, "scans": len(specs),
+            "batched_ms": t_batch, "sequential_ms": t_seq,
+            "batched_histories_per_s": total / (t_batch * 1e-3),
+            "sequential_histories_per_s": total / (t_seq * 1e-3),
+            "speedup": t_seq / t_batch,
+            "tuning": {"streams": tune.streams, "use_graph": tune.use_graph,
+                       "walk_blocks": tune.walk_blocks},
+            "plan_s_incl_autotune": t_plan_s}
+
+
+def bench_serve(torch, gen, H, full=False):
+    """Requests arriving one by one with their histories in (pinned) host
+    memory, leaving as masks in host memory. Rules SC : MSC : SM = 1 : 1 : 1,
+    grids 128x128x32 / 200x200x32 / 256x256x64, log-uniform history counts.
+    A calibration pass measures the sequential capacity; the recorded trace
+    then arrives as a Poisson process at 0.7 of it. Latency = arrival to masks
+    on the host (copies included); device_ms = copy-in to copy-out on the
+    worker's stream. The same trace served one request at a time is the
+    sequential baseline."""
+    import threading
+    import numpy as np
+    h_hi = 1e8 if full else 1e7
+    n_req, warm = (2000, 100) if full else (300, 30)
+    rng = np.random.default_rng(0x5EED0005)
+    grids = gen.BATCH_GRIDS[1:]
+    pools = []
+    for gi, g in enumerate(grids):
+        sp = gen.ScanSpec(g, int(h_hi), 180, gen.head_phantom(g, inserts=g.n[0] >= 200),
+                          0x5EED0005 + 100 * (gi + 1), sigma=3.0)
+        h = gen.generate(sp)
+        perm = rng.permutation(sp.n_hist)     # any prefix is then a uniform subsample
+        pool = {}
+        for k in H.FIELDS:
+            t = torch.empty(sp.n_hist, dtype=torch.float32, pin_memory=True)
+            a = t.numpy()
+            np.take(h[k], perm, out=a)
+            pool[k] = (t, a)
+        del h
+        pools.append(pool)
+    ops = (H.HULL_OP_SC, H.HULL_OP_MSC, H.HULL_OP_SM)
+    mask_of = {H.HULL_OP_SC: "sc_mask", H.HULL_OP_MSC: "msc_mask", H.HULL_OP_SM: "sm_mask"}
+    trace = []
+    for _ in range(warm + n_req):
+        gi = int(rng.integers(len(grids)))
+        n = int(round(np.exp(rng.uniform(np.log(1e5), np.log(h_hi)))))
+        trace.append((int(rng.choice(ops)), gi, n))
+    params = H.make_params()
+
+    def submit(srv, req):
+        op, gi, n = req
+        hist = {k: pools[gi][k][1][:n] for k in H.FIELDS}
+        out = {mask_of[op]: np.empty(grids[gi].voxels, dtype=np.uint8)}
+        return srv.submit(op, hist, grids[gi], params, **out)
+
+    srv = H.Server(hbm_budget=48 << 30, max_slots=4)
+    # calibration: the warm-up part of the trace, one request at a time
+    svc = []
+    for req in trace[:warm]:
+        r = srv.wait(submit(srv, req))
+        svc.append((r["t_done_ns"] - r["t_arrive_ns"]) * 1e-9)
+    cap = 1.0 / float(np.mean(svc[len(svc) // 3:]))
+    lam = 0.7 * cap
+    rec = trace[warm:]
+    gaps = rng.exponential(1.0 / lam, size=len(rec))
+    tickets = [None] * len(rec)
+
+    def producer():
+        t = time.perf_counter()
+        for i, req in enumerate(rec):
+            t += gaps[i]
+            d = t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = submit(srv, req)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    res = []
+    for i in range(len(rec)):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        res.append(srv.wait(tickets[i]))
+    th.join()
+    lat = np.array([(r["t_done_ns"] - r["t_arrive_ns"]) * 1e-6 for r in res])
+    dev_ms = np.array([r["device_ms"] for r in res])
+    span = (max(r["t_done_ns"] for r in res) - min(r["t_arrive_ns"] for r in res)) * 1e-9
+    hist_total = sum(n for _, _, n in rec)
+    ok = all(r["status"] == H.HULL_OK for r in res)
+    # sequential baseline on the same trace
+    seq = []
+    for req in rec:
+        r = srv.wait(submit(srv, req))
+        seq.append((r["t_done_ns"] - r["t_arrive_ns"]) * 1e-9)
+    st = srv.stats()
+    srv.close()
+    return {"workload": f"{n_req} requests after {warm} warm-up, log-uniform 1e5..{h_hi:.0e} "
+                        "histories, SC:MSC:SM 1:1:1, grids 128x128x32 / 200x200x32 / 256x256x64, "
+                        "pinned host inputs, masks back on the host",
+            "all_ok": ok, "lambda_req_per_s": lam, "sequential_capacity_req_per_s": cap,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99))},
+            "device_ms": {"p50": float(np.percentile(dev_ms, 50)),
+                          "p99": float(np.percentile(dev_ms, 99))},
+            "served_histories_per_s": hist_total / span,
+            "sequential_histories_per_s": hist_total / float(np.sum(seq)),
+            "sequential_latency_ms_p50": float(np.percentile(np.array(seq) * 1e3, 50)),
+            "arena_peak_bytes": st["bytes_peak"], "slots": 4}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +225,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 16-scan batch figures")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving figures")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serve 2000 requests of up to 1e8 histories (minutes) instead of 300 of "
+                         "up to 1e7")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one 256 MiB device-to-device copy: the "
                          "known-size kernel that scales hardware byte counters")
@@ -206,6 +371,18 @@ def main():
                      "traffic": measured_traffic()},
         "cpu_baseline": None,
     }
+
+    # free the single-scan buffers before the batch and serving figures
+    del hist, N, M, sc, msc, sm, fmask, image, ws_all, ws_fbp
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        log("batch: 16 scans")
+        result["batch"] = bench_batch(torch, gen, H, dev)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("serving")
+        result["serving"] = bench_serve(torch, gen, H, full=args.serve_full)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         import oracle

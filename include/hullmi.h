@@ -215,6 +215,151 @@ int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n,
 int hull_quantize(const hullmi_histories *hist, const hullmi_grid *grid, int32_t *status,
                   int32_t *q_in, int32_t *q_out, void *stream);
 
+/* Device bytes that one request of `op` (HULL_OP_SC, _MSC, _SM, _ALL or _FBP)
+ * occupies when the library holds everything itself, as the server does: the
+ * eight input arrays (n values each), every output of the op (counts, masks,
+ * FBP image), the stats block and the op's workspace, each piece 256-byte
+ * aligned. fbp may be NULL unless op is HULL_OP_FBP. (size_t)-1 on invalid
+ * arguments. Servers admit requests by this figure against their budget. */
+size_t hull_footprint_bytes(int op, const hullmi_grid *grid, int64_t n,
+                            const hullmi_fbp_params *fbp);
+
+/* ------------------------------------------------------------------------
+ * Batches: many scans, planned once and launched as one unit.
+ *
+ * The scans are independent (every history is its own line, Section 3), so a
+ * plan spreads its jobs over several internal streams, longest first onto the
+ * least loaded stream, each stream with a workspace of its own, and on the
+ * first launch captures the whole fork/join into a HIP graph that later
+ * launches replay. A job is one per-scan call with device pointers exactly
+ * as hull_sc / hull_msc / hull_sm / hull_all / hull_fbp take them.
+ * ---------------------------------------------------------------------- */
+
+/* One scan of a batch. op selects the call; only the fields that call reads
+ * matter: SC reads params.wepl_low and writes N (+ sc_mask); MSC reads
+ * params.wepl_low / msc_n_t / msc_mode / nbr and writes N (+ msc_mask); SM
+ * reads params.wepl_high / sm_* / nbr and writes M (+ sm_mask); ALL is
+ * hull_all; FBP reads fbp and writes image (+ fbp_mask). Pointers are device
+ * pointers owned by the caller and must stay valid until the plan is
+ * destroyed; their contents may change between launches. */
+typedef struct hullmi_job {
+    int32_t op;
+    uint32_t flags;
+    hullmi_histories hist;
+    hullmi_grid grid;
+    hullmi_params params;
+    hullmi_fbp_params fbp;
+    int32_t *N, *M;
+    uint8_t *sc_mask, *msc_mask, *sm_mask;
+    float *image;
+    uint8_t *fbp_mask;
+    hullmi_stats *stats;
+} hullmi_job;
+
+/* Launch choices of a plan. streams: concurrent internal streams (1..16);
+ * use_graph: capture on the first launch and replay afterwards (0 / 1);
+ * walk_blocks: cap on the workgroups of each persistent walk (0 = one per
+ * resident slot of the device). */
+typedef struct hullmi_tuning {
+    int32_t streams;
+    int32_t use_graph;
+    int32_t walk_blocks;
+} hullmi_tuning;
+
+typedef struct hullmi_plan hullmi_plan;
+
+/* Checks every job as its per-scan call would (HULL_EINVAL on the first bad
+ * one, nothing enqueued), allocates one workspace per internal stream and
+ * assigns jobs to streams. With tuning == NULL the choice comes from a
+ * per-process cache keyed by the job shapes; on a miss, when no job has
+ * HULL_ACCUMULATE, a few candidate tunings are timed by running the batch
+ * (outputs are written), else a fixed default is used. Must be called with
+ * the device of the job pointers current. */
+int hull_batch_plan(const hullmi_job *jobs, int n_jobs, const hullmi_tuning *tuning,
+                    hullmi_plan **plan);
+
+/* Enqueues every job of the plan on `stream`: work starts after what is
+ * already on `stream` and everything the plan does is complete before later
+ * work on `stream` starts. Launches of one plan must not overlap. */
+int hull_batch_launch(hullmi_plan *plan, void *stream);
+
+/* The tuning the plan uses. */
+int hull_batch_tuning(const hullmi_plan *plan, hullmi_tuning *out);
+
+/* Waits for the plan's streams, frees its memory. NULL is ignored. */
+int hull_batch_destroy(hullmi_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Serving: scans arrive one by one from the host and leave as masks on the
+ * host.
+ *
+ * A server owns one device arena of hbm_budget bytes and max_slots worker
+ * threads, each with its own stream. Requests queue in arrival order; a free
+ * worker admits the request at the head of the queue as soon as its
+ * footprint (hull_footprint_bytes) fits in the arena, copies its histories
+ * in, runs its call, copies the outputs out and frees its space, so new
+ * requests join while others are still running. Requests never share device
+ * memory, so a request's result does not depend on what else is running.
+ * ---------------------------------------------------------------------- */
+
+/* One request. Histories and outputs are HOST pointers owned by the caller,
+ * valid until hull_server_wait has returned for the ticket (pinned host
+ * memory gives the full copy rate; pageable works). Outputs may be NULL when
+ * not wanted; op and parameters as in hullmi_job. */
+typedef struct hullmi_request {
+    int32_t op;
+    hullmi_histories hist;
+    hullmi_grid grid;
+    hullmi_params params;
+    hullmi_fbp_params fbp;
+    int32_t *N, *M;
+    uint8_t *sc_mask, *msc_mask, *sm_mask;
+    float *image;
+    uint8_t *fbp_mask;
+} hullmi_request;
+
+/* Outcome of a request. Times are steady-clock nanoseconds of the host:
+ * arrival (submit), admission (space granted), done (outputs on the host).
+ * device_ms runs from the first input copy to the last output copy on the
+ * worker's stream; compute_ms covers the call alone. */
+typedef struct hullmi_result {
+    int32_t status;
+    hullmi_stats stats;
+    int64_t t_arrive_ns, t_admit_ns, t_done_ns;
+    float device_ms, h2d_ms, compute_ms, d2h_ms;
+} hullmi_result;
+
+typedef struct hullmi_server_stats {
+    int64_t submitted, completed, failed, queued, running;
+    int64_t histories_done;
+    uint64_t bytes_budget, bytes_in_use, bytes_peak;
+} hullmi_server_stats;
+
+typedef struct hullmi_server hullmi_server;
+
+/* Creates a server on `device` with an arena of hbm_budget bytes (allocated
+ * here, once) and max_slots (1..64) workers. HULL_ENOMEM when the arena cannot
+ * be allocated, HULL_EDEVICE when the device cannot be used. */
+int hull_server_create(size_t hbm_budget, int max_slots, int device, hullmi_server **srv);
+
+/* Validates and queues a request; returns at once with its ticket.
+ * HULL_EINVAL for bad arguments, HULL_ENOMEM when its footprint exceeds the
+ * whole budget (it could never be admitted), HULL_EBUSY after destroy began. */
+int hull_server_submit(hullmi_server *srv, const hullmi_request *req, uint64_t *ticket);
+
+/* Waits up to timeout_us microseconds (negative: no limit) for a ticket.
+ * HULL_OK with *result filled (result->status is the call's own status) and
+ * the ticket retired; HULL_ETIMEDOUT when it is still queued or running;
+ * HULL_EINVAL for an unknown or retired ticket. */
+int hull_server_wait(hullmi_server *srv, uint64_t ticket, hullmi_result *result,
+                     int64_t timeout_us);
+
+int hull_server_stats(hullmi_server *srv, hullmi_server_stats *out);
+
+/* Finishes the requests already admitted, drops the ones still queued and
+ * frees everything. NULL is ignored. */
+int hull_server_destroy(hullmi_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

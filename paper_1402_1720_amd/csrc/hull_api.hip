@@ -11,6 +11,7 @@
 #include "hull_binned.h"
 #include "hull_device.h"
 #include "hull_kernels.h"
+#include "hull_runtime.h"
 #include "hullmi.h"
 
 namespace hullmi {
@@ -120,6 +121,25 @@ DevProps dev_props()
     return p;
 }
 
+// Raises a kernel's dynamic LDS limit to all that its static LDS leaves free
+// and returns that limit (0 when it cannot be set). The value depends only on
+// the kernel and the device, so concurrent calls on different grids never
+// lower it under each other's launches.
+size_t allow_max_lds(const void *fn, size_t max_lds)
+{
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, fn) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const size_t lim = max_lds > a.sharedSizeBytes ? max_lds - a.sharedSizeBytes : 0;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return lim;
+}
+
 inline int64_t plane_of(const hullmi_grid *g) { return (int64_t)g->nx * g->ny; }
 
 // A slice fits the LDS tile when its 16-bit counters fit kMaxTileVoxels.
@@ -172,7 +192,7 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.range_piece = reinterpret_cast<uint32_t *>(take((size_t)(w.max_ranges + 1) * 4));
     w.wprefix = reinterpret_cast<unsigned long long *>(take((size_t)(w.nsub + 1) * 8));
     w.ctl = reinterpret_cast<int32_t *>(take((size_t)kCtlWords * 4));
-    w.items = reinterpret_cast<uint32_t *>(take((size_t)imax * 4));
+    w.rec = reinterpret_cast<int32_t *>(take((size_t)imax * 24));
     w.partial = reinterpret_cast<uint32_t *>(
         take(tile_fits(g) ? (size_t)w.max_slots * w.tile_words * 4 : 0));
     if (bytes) *bytes = off;
@@ -214,7 +234,8 @@ FbpWs fbp_ws_layout(const hullmi_fbp_params *p, void *base)
 // Zero (unless accumulating) and count: the shared core of every hull call.
 // Histories go through in batches of up to kBatch; counts add up across them.
 int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, float e_high, int32_t *N,
-               int32_t *M, uint32_t flags, hullmi_stats *stats, void *ws, hipStream_t s)
+               int32_t *M, uint32_t flags, hullmi_stats *stats, void *ws, hipStream_t s,
+               int walk_blocks)
 {
     const int64_t V = voxels(g);
     if (!(flags & HULL_ACCUMULATE)) {
@@ -226,17 +247,18 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
     BinWs w = bin_ws_layout(g, h->n, ws, nullptr);
     const DevProps dp = dev_props();
     const size_t tile_bytes = (size_t)w.tile_words * 4 + 16;   // tile + control words
-    const bool tile_ok = tile_fits(g) && tile_bytes <= dp.max_lds;
+    const bool tile_ok =
+        tile_fits(g) &&
+        tile_bytes <= allow_max_lds(reinterpret_cast<const void *>(k_walk_tiles), dp.max_lds);
     int per_cu = 1;
     if (tile_ok) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_walk_tiles),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_bytes);
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_walk_tiles, kTileThreads,
                                                          tile_bytes) == hipSuccess && occ > 0)
             per_cu = occ;
     }
-    const int walk_grid = std::min(dp.cus * per_cu, kMinRanges);
+    int walk_grid = std::min(dp.cus * per_cu, kMinRanges);
+    if (walk_blocks > 0) walk_grid = std::min(walk_grid, walk_blocks);
     const DevGrid dg = dev_grid(g);
     const int plane = (int)plane_of(g);
     for (int64_t h0 = 0; h0 < h->n; h0 += w.B) {
@@ -303,7 +325,211 @@ bool sm_args_ok(int num, int den, int mode, int scope, int nbr)
            (nbr == HULL_NBR_INPLANE4 || nbr == HULL_NBR_SPATIAL6);
 }
 
+int sc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t *N,
+            uint8_t *mask, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
+            hipStream_t s, int walk_blocks)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low)) return HULL_EINVAL;
+    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, walk_blocks);
+    if (rc != HULL_OK) return rc;
+    if (mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, mask, voxels(grid));
+    return launch_status();
+}
+
+int msc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t n_t,
+             int mode, int nbr, int32_t *N, uint8_t *mask, uint32_t flags, hullmi_stats *stats,
+             void *ws, size_t ws_bytes, hipStream_t s, int walk_blocks)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low) ||
+        !msc_args_ok(n_t, mode, nbr))
+        return HULL_EINVAL;
+    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, walk_blocks);
+    if (rc != HULL_OK) return rc;
+    return run_msc_mask(grid, N, mask, n_t, mode, nbr, s);
+}
+
+int sm_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_high, int32_t frac_num,
+            int32_t frac_den, int mode, int scope, int nbr, int32_t *M, uint8_t *mask,
+            uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, hipStream_t s,
+            int walk_blocks)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !M || !std::isfinite(wepl_high) ||
+        !sm_args_ok(frac_num, frac_den, mode, scope, nbr))
+        return HULL_EINVAL;
+    const size_t cw = counts_ws_bytes(grid, hist->n);
+    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, ws, s, walk_blocks);
+    if (rc != HULL_OK) return rc;
+    return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr,
+                       reinterpret_cast<char *>(ws) + cw, s);
+}
+
+int all_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
+             int32_t *N, int32_t *M, uint8_t *sc_mask, uint8_t *msc_mask, uint8_t *sm_mask,
+             uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, hipStream_t s,
+             int walk_blocks)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !p || !N || !M) return HULL_EINVAL;
+    if (!std::isfinite(p->wepl_low) || !std::isfinite(p->wepl_high)) return HULL_EINVAL;
+    if (msc_mask && !msc_args_ok(p->msc_n_t, p->msc_mode, p->nbr)) return HULL_EINVAL;
+    if (sm_mask && !sm_args_ok(p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr))
+        return HULL_EINVAL;
+    const size_t cw = counts_ws_bytes(grid, hist->n);
+    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, ws, s,
+                        walk_blocks);
+    if (rc != HULL_OK) return rc;
+    if (sc_mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, sc_mask, voxels(grid));
+    rc = launch_status();
+    if (rc == HULL_OK) rc = run_msc_mask(grid, N, msc_mask, p->msc_n_t, p->msc_mode, p->nbr, s);
+    if (rc == HULL_OK)
+        rc = run_sm_mask(grid, M, sm_mask, p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope,
+                         p->nbr, reinterpret_cast<char *>(ws) + cw, s);
+    return rc;
+}
+
+int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+             float *image, uint8_t *mask, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image) return HULL_EINVAL;
+    const size_t need = fbp_ws_layout(fbp, nullptr).bytes;
+    if (!ws || ws_bytes < need) return HULL_ENOMEM;
+    FbpWs w = fbp_ws_layout(fbp, ws);
+    FbpDev p;
+    p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
+    p.u0 = fbp->u0_mm; p.v0 = fbp->v0_mm;
+    p.rdu = 1.0f / fbp->du_mm; p.rdv = 1.0f / fbp->dv_mm; p.rda = 1.0f / fbp->dangle_deg;
+    p.angle0 = fbp->angle0_deg; p.dangle = fbp->dangle_deg; p.threshold = fbp->threshold;
+    p.half_dth = (float)(0.5 * (double)fbp->dangle_deg * 3.14159265358979323846 / 180.0);
+    p.nu = fbp->nu; p.nv = fbp->nv; p.n_angles = fbp->n_angles;
+    const int64_t nb = (int64_t)p.nu * p.nv * p.n_angles;
+    fill_u64(w.sum, 0ull, nb, s);
+    fill_u32(w.cnt, 0u, nb, s);
+    if (hist->n > 0) {
+        const size_t plane_lds = (size_t)p.nu * p.nv * 12;
+        if (plane_lds <= allow_max_lds(reinterpret_cast<const void *>(k_fbp_bin_lds),
+                                       dev_props().max_lds)) {
+            const int64_t chunk = 32768;
+            k_fbp_bin_lds<<<(unsigned)((hist->n + chunk - 1) / chunk), kBlock, plane_lds, s>>>(
+                *hist, p, w.sum, w.cnt, chunk);
+        } else {
+            k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
+        }
+    }
+    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(double);
+    fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
+    k_fbp_filter<<<(unsigned)(p.n_angles * p.nv), kBlock, lds, s>>>(w.sum, w.cnt, w.q, p);
+    k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
+    FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
+                  grid->x0, grid->y0, grid->z0};
+    const int64_t ncol = (int64_t)grid->nx * grid->ny * ((grid->nz + 7) / 8);
+    k_fbp_backproject<<<blocks_for(ncol), kBlock, 0, s>>>(w.q, w.cs, p, gd, image, mask);
+    return launch_status();
+}
+
+size_t ws_bytes_of(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_params *fbp)
+{
+    if (n < 0) return (size_t)-1;
+    switch (op) {
+    case HULL_OP_COUNT_LINES:
+        if (!grid_ok(grid)) return (size_t)-1;
+        return 0;
+    case HULL_OP_SC:
+    case HULL_OP_MSC:
+        if (!grid_ok(grid)) return (size_t)-1;
+        return counts_ws_bytes(grid, n);
+    case HULL_OP_SM:
+    case HULL_OP_ALL:
+        if (!grid_ok(grid)) return (size_t)-1;
+        return counts_ws_bytes(grid, n) + sm_ws_bytes(grid);
+    case HULL_OP_FBP:
+        if (!grid_ok(grid) || !fbp_ok(fbp)) return (size_t)-1;
+        return fbp_ws_layout(fbp, nullptr).bytes;
+    default:
+        return (size_t)-1;
+    }
+}
+
 }  // namespace
+
+// ---- shared with the batch and server runtime ----
+
+size_t job_ws_bytes(const hullmi_job &j)
+{
+    return ws_bytes_of(j.op, &j.grid, j.hist.n, j.op == HULL_OP_FBP ? &j.fbp : nullptr);
+}
+
+int job_check(const hullmi_job &j)
+{
+    if (!hist_ok(&j.hist) || !grid_ok(&j.grid)) return HULL_EINVAL;
+    const hullmi_params &p = j.params;
+    switch (j.op) {
+    case HULL_OP_SC:
+        return j.N && std::isfinite(p.wepl_low) ? HULL_OK : HULL_EINVAL;
+    case HULL_OP_MSC:
+        return j.N && std::isfinite(p.wepl_low) && msc_args_ok(p.msc_n_t, p.msc_mode, p.nbr)
+                   ? HULL_OK : HULL_EINVAL;
+    case HULL_OP_SM:
+        return j.M && std::isfinite(p.wepl_high) &&
+                       sm_args_ok(p.sm_frac_num, p.sm_frac_den, p.sm_mode, p.sm_scope, p.nbr)
+                   ? HULL_OK : HULL_EINVAL;
+    case HULL_OP_ALL:
+        if (!j.N || !j.M || !std::isfinite(p.wepl_low) || !std::isfinite(p.wepl_high))
+            return HULL_EINVAL;
+        if (j.msc_mask && !msc_args_ok(p.msc_n_t, p.msc_mode, p.nbr)) return HULL_EINVAL;
+        if (j.sm_mask && !sm_args_ok(p.sm_frac_num, p.sm_frac_den, p.sm_mode, p.sm_scope, p.nbr))
+            return HULL_EINVAL;
+        return HULL_OK;
+    case HULL_OP_FBP:
+        return j.image && fbp_ok(&j.fbp) ? HULL_OK : HULL_EINVAL;
+    default:
+        return HULL_EINVAL;
+    }
+}
+
+int job_run(const hullmi_job &j, void *ws, size_t ws_bytes, hipStream_t s, int walk_blocks)
+{
+    const hullmi_params &p = j.params;
+    switch (j.op) {
+    case HULL_OP_SC:
+        return sc_impl(&j.hist, &j.grid, p.wepl_low, j.N, j.sc_mask, j.flags, j.stats, ws, ws_bytes,
+                       s, walk_blocks);
+    case HULL_OP_MSC:
+        return msc_impl(&j.hist, &j.grid, p.wepl_low, p.msc_n_t, p.msc_mode, p.nbr, j.N,
+                        j.msc_mask, j.flags, j.stats, ws, ws_bytes, s, walk_blocks);
+    case HULL_OP_SM:
+        return sm_impl(&j.hist, &j.grid, p.wepl_high, p.sm_frac_num, p.sm_frac_den, p.sm_mode,
+                       p.sm_scope, p.nbr, j.M, j.sm_mask, j.flags, j.stats, ws, ws_bytes, s,
+                       walk_blocks);
+    case HULL_OP_ALL:
+        return all_impl(&j.hist, &j.grid, &p, j.N, j.M, j.sc_mask, j.msc_mask, j.sm_mask, j.flags,
+                        j.stats, ws, ws_bytes, s, walk_blocks);
+    case HULL_OP_FBP:
+        return fbp_impl(&j.hist, &j.grid, &j.fbp, j.image, j.fbp_mask, ws, ws_bytes, s);
+    default:
+        return HULL_EINVAL;
+    }
+}
+
+size_t footprint_bytes(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_params *fbp)
+{
+    if (op < HULL_OP_SC || op > HULL_OP_FBP || n < 0 || n > INT32_MAX) return (size_t)-1;
+    const size_t ws = ws_bytes_of(op, grid, n, fbp);
+    if (ws == (size_t)-1) return ws;
+    const size_t V = (size_t)voxels(grid);
+    size_t out = 0;
+    switch (op) {
+    case HULL_OP_SC:
+    case HULL_OP_MSC:
+    case HULL_OP_SM: out = align_up(4 * V) + align_up(V); break;
+    case HULL_OP_ALL: out = 2 * align_up(4 * V) + 3 * align_up(V); break;
+    case HULL_OP_FBP: out = align_up(4 * V) + align_up(V); break;
+    }
+    return 8 * align_up(4 * (size_t)n) + out + align_up(sizeof(hullmi_stats)) + align_up(ws);
+}
+
 }  // namespace hullmi
 
 using namespace hullmi;
@@ -328,132 +554,49 @@ const char *hull_strerror(int status)
 
 size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_params *fbp)
 {
-    if (n < 0) return (size_t)-1;
-    switch (op) {
-    case HULL_OP_COUNT_LINES:
-        if (!grid_ok(grid)) return (size_t)-1;
-        return 0;
-    case HULL_OP_SC:
-    case HULL_OP_MSC:
-        if (!grid_ok(grid)) return (size_t)-1;
-        return counts_ws_bytes(grid, n);
-    case HULL_OP_SM:
-    case HULL_OP_ALL:
-        if (!grid_ok(grid)) return (size_t)-1;
-        return counts_ws_bytes(grid, n) + sm_ws_bytes(grid);
-    case HULL_OP_FBP:
-        if (!grid_ok(grid) || !fbp_ok(fbp)) return (size_t)-1;
-        return fbp_ws_layout(fbp, nullptr).bytes;
-    default:
-        return (size_t)-1;
-    }
+    return ws_bytes_of(op, grid, n, fbp);
+}
+
+size_t hull_footprint_bytes(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_params *fbp)
+{
+    return footprint_bytes(op, grid, n, fbp);
 }
 
 int hull_sc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t *N,
             uint8_t *mask, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
             void *stream)
 {
-    if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low)) return HULL_EINVAL;
-    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
-    hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s);
-    if (rc != HULL_OK) return rc;
-    if (mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, mask, voxels(grid));
-    return launch_status();
+    return sc_impl(hist, grid, wepl_low, N, mask, flags, stats, ws, ws_bytes, as_stream(stream), 0);
 }
 
 int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t n_t,
              int mode, int nbr, int32_t *N, uint8_t *mask, uint32_t flags, hullmi_stats *stats,
              void *ws, size_t ws_bytes, void *stream)
 {
-    if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low) ||
-        !msc_args_ok(n_t, mode, nbr))
-        return HULL_EINVAL;
-    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
-    hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s);
-    if (rc != HULL_OK) return rc;
-    return run_msc_mask(grid, N, mask, n_t, mode, nbr, s);
+    return msc_impl(hist, grid, wepl_low, n_t, mode, nbr, N, mask, flags, stats, ws, ws_bytes,
+                    as_stream(stream), 0);
 }
 
 int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_high, int32_t frac_num,
             int32_t frac_den, int mode, int scope, int nbr, int32_t *M, uint8_t *mask,
             uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!hist_ok(hist) || !grid_ok(grid) || !M || !std::isfinite(wepl_high) ||
-        !sm_args_ok(frac_num, frac_den, mode, scope, nbr))
-        return HULL_EINVAL;
-    const size_t cw = counts_ws_bytes(grid, hist->n);
-    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
-    hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, ws, s);
-    if (rc != HULL_OK) return rc;
-    return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr,
-                       reinterpret_cast<char *>(ws) + cw, s);
+    return sm_impl(hist, grid, wepl_high, frac_num, frac_den, mode, scope, nbr, M, mask, flags,
+                   stats, ws, ws_bytes, as_stream(stream), 0);
 }
 
 int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
              int32_t *N, int32_t *M, uint8_t *sc_mask, uint8_t *msc_mask, uint8_t *sm_mask,
              uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!hist_ok(hist) || !grid_ok(grid) || !p || !N || !M) return HULL_EINVAL;
-    if (!std::isfinite(p->wepl_low) || !std::isfinite(p->wepl_high)) return HULL_EINVAL;
-    if (msc_mask && !msc_args_ok(p->msc_n_t, p->msc_mode, p->nbr)) return HULL_EINVAL;
-    if (sm_mask && !sm_args_ok(p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr))
-        return HULL_EINVAL;
-    const size_t cw = counts_ws_bytes(grid, hist->n);
-    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
-    hipStream_t s = as_stream(stream);
-    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, ws, s);
-    if (rc != HULL_OK) return rc;
-    if (sc_mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, sc_mask, voxels(grid));
-    rc = launch_status();
-    if (rc == HULL_OK) rc = run_msc_mask(grid, N, msc_mask, p->msc_n_t, p->msc_mode, p->nbr, s);
-    if (rc == HULL_OK)
-        rc = run_sm_mask(grid, M, sm_mask, p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope,
-                         p->nbr, reinterpret_cast<char *>(ws) + cw, s);
-    return rc;
+    return all_impl(hist, grid, p, N, M, sc_mask, msc_mask, sm_mask, flags, stats, ws, ws_bytes,
+                    as_stream(stream), 0);
 }
 
 int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
              float *image, uint8_t *mask, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image) return HULL_EINVAL;
-    const size_t need = fbp_ws_layout(fbp, nullptr).bytes;
-    if (!ws || ws_bytes < need) return HULL_ENOMEM;
-    hipStream_t s = as_stream(stream);
-    FbpWs w = fbp_ws_layout(fbp, ws);
-    FbpDev p;
-    p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
-    p.u0 = fbp->u0_mm; p.v0 = fbp->v0_mm;
-    p.rdu = 1.0f / fbp->du_mm; p.rdv = 1.0f / fbp->dv_mm; p.rda = 1.0f / fbp->dangle_deg;
-    p.angle0 = fbp->angle0_deg; p.dangle = fbp->dangle_deg; p.threshold = fbp->threshold;
-    p.half_dth = (float)(0.5 * (double)fbp->dangle_deg * 3.14159265358979323846 / 180.0);
-    p.nu = fbp->nu; p.nv = fbp->nv; p.n_angles = fbp->n_angles;
-    const int64_t nb = (int64_t)p.nu * p.nv * p.n_angles;
-    fill_u64(w.sum, 0ull, nb, s);
-    fill_u32(w.cnt, 0u, nb, s);
-    if (hist->n > 0) {
-        const size_t plane_lds = (size_t)p.nu * p.nv * 12;
-        if (plane_lds <= dev_props().max_lds) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_fbp_bin_lds),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane_lds);
-            const int64_t chunk = 32768;
-            k_fbp_bin_lds<<<(unsigned)((hist->n + chunk - 1) / chunk), kBlock, plane_lds, s>>>(
-                *hist, p, w.sum, w.cnt, chunk);
-        } else {
-            k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
-        }
-    }
-    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(double);
-    fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
-    k_fbp_filter<<<(unsigned)(p.n_angles * p.nv), kBlock, lds, s>>>(w.sum, w.cnt, w.q, p);
-    k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
-    FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
-                  grid->x0, grid->y0, grid->z0};
-    const int64_t ncol = (int64_t)grid->nx * grid->ny * ((grid->nz + 7) / 8);
-    k_fbp_backproject<<<blocks_for(ncol), kBlock, 0, s>>>(w.q, w.cs, p, gd, image, mask);
-    return launch_status();
+    return fbp_impl(hist, grid, fbp, image, mask, ws, ws_bytes, as_stream(stream));
 }
 
 int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n, const hullmi_grid *grid,

@@ -1,5 +1,5 @@
 // Slice-binned counting: the (history, z-slice) items of a batch are sorted by
-// (class, slice, length class); a persistent grid of workgroups takes
+// (class, slice, length class), each stored with its line's endpoints; a persistent grid of workgroups takes
 // contiguous ranges of equal estimated work from that list and accumulates
 // each slice it meets in a 16-bit LDS copy, written out as a partial tile when
 // its range leaves the slice; a reduction then adds the partials into N or M.
@@ -46,7 +46,7 @@ struct BinWs {
     uint32_t *range_piece;  // [max_ranges] first final range of each coarse range
     unsigned long long *wprefix;  // [nsub + 1] work prefix of the sub-bins
     int32_t *ctl;           // kCtlWords
-    uint32_t *items;        // [B * kMaxSlicesPerLine] history of each (history, slice) item
+    int32_t *rec;           // [B * kMaxSlicesPerLine][6] endpoints of each (history, slice) item
     uint32_t *partial;      // [max_slots][tile_words]
     int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
     int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;

@@ -4,7 +4,8 @@
 //   scan     : per sub-bin offsets of every block
 //   plan     : sub-bin starts, slice (tile) starts, ranges of equal estimated
 //              work over the sorted item list
-//   scatter  : (history, slice) items in sub-bin order
+//   scatter  : (history, slice) items in sub-bin order, each a copy of the
+//              history's 24-byte endpoint record
 //   walk     : persistent workgroups; each range is cut at slice boundaries
 //              into segments, each accumulated in a 16-bit LDS copy of its
 //              slice and written to its own partial slot
@@ -96,6 +97,10 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x) lh[b] = 0;
     __syncthreads();
     unsigned long long nl = 0, nh = 0, nsk = 0, nmi = 0;
+    // cosine and sine of the last angle seen by this thread: histories come
+    // in long runs of one gantry angle, and equal angle bits give equal c, s
+    uint32_t trig_bits = 0x7fc00001u;   // a NaN: finite angles never match it
+    float tc = 1.0f, ts = 0.0f;
     const int64_t base = (int64_t)blockIdx.x * kHistPerBlock;
     for (int r = 0; r < kHistPerThread; ++r) {
         const int64_t j = base + (int64_t)r * kBinThreads + threadIdx.x;
@@ -118,10 +123,12 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                               ? kGeoOk
                               : kGeoNonFinite;
                 if (stg == kGeoOk) {
-                    float c, s;
-                    deg_cos_sin(a, c, s);
-                    stg = quantize_point(c, s, xi, yi, zi, g, q[0], q[1], q[2]);
-                    if (stg == kGeoOk) stg = quantize_point(c, s, xo, yo, zo, g, q[3], q[4], q[5]);
+                    if (__float_as_uint(a) != trig_bits) {
+                        deg_cos_sin(a, tc, ts);
+                        trig_bits = __float_as_uint(a);
+                    }
+                    stg = quantize_point(tc, ts, xi, yi, zi, g, q[0], q[1], q[2]);
+                    if (stg == kGeoOk) stg = quantize_point(tc, ts, xo, yo, zo, g, q[3], q[4], q[5]);
                     if (stg == kGeoOk && q[0] == q[3] && q[1] == q[4] && q[2] == q[5])
                         stg = kGeoDegenerate;
                 }
@@ -313,16 +320,20 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
         const uint32_t m = w.meta[j];
         if (!(m & kMetaValid)) continue;
         const int cls = (m & kMetaHigh) ? 1 : 0;
+        const int2 *src = reinterpret_cast<const int2 *>(w.q + 6 * j);
+        const int2 a = src[0], b = src[1], c = src[2];
+        auto put = [&](uint32_t p) {
+            int2 *dst = reinterpret_cast<int2 *>(w.rec + 6 * (size_t)p);
+            dst[0] = a; dst[1] = b; dst[2] = c;
+        };
         if (m & kMetaOverflow) {
-            const uint32_t p = atomicAdd(&cur[w.nsub - 2 + cls], 1u);
-            w.items[p] = (uint32_t)j;
+            put(atomicAdd(&cur[w.nsub - 2 + cls], 1u));
         } else {
             const int k0 = (int)(m & 0xfffu), ns = (int)((m >> 12) & 0xfffu);
             const uint32_t lp = w.lpack[j];
             for (int k = k0; k < k0 + ns; ++k) {
                 const int lc = (int)((lp >> (4 * (k - k0))) & 0xfu);
-                const uint32_t p = atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u);
-                w.items[p] = (uint32_t)j;
+                put(atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u));
             }
         }
     }
@@ -368,23 +379,21 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
             const int t = (int)seg[0];
             const uint32_t y = seg[1], slot = seg[2];
             const int k = t % w.nz;
-            // two-deep prefetch: the history index two items ahead and the
-            // endpoint record one item ahead are in flight during a walk
+            // the next item's record (contiguous across the workgroup) is in
+            // flight while the current line is walked
             const uint32_t S = blockDim.x;
             uint32_t it = x + threadIdx.x;
             int2 c0 = make_int2(0, 0), c1 = c0, c2 = c0;
             if (it < y) {
-                const int2 *r = reinterpret_cast<const int2 *>(w.q + 6 * (size_t)w.items[it]);
+                const int2 *r = reinterpret_cast<const int2 *>(w.rec + 6 * (size_t)it);
                 c0 = r[0]; c1 = r[1]; c2 = r[2];
             }
-            uint32_t jn = it + S < y ? w.items[it + S] : 0u;
             while (it < y) {
                 const int2 a0 = c0, a1 = c1, a2 = c2;
                 if (it + S < y) {
-                    const int2 *r = reinterpret_cast<const int2 *>(w.q + 6 * (size_t)jn);
+                    const int2 *r = reinterpret_cast<const int2 *>(w.rec + 6 * (size_t)(it + S));
                     c0 = r[0]; c1 = r[1]; c2 = r[2];
                 }
-                jn = it + 2 * S < y ? w.items[it + 2 * S] : 0u;
                 walk_slice_tile16(a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, nx, ny, k, tile_base, acc);
                 it += S;
             }
@@ -461,7 +470,7 @@ k_walk_overflow(BinWs w, int nx, int ny, int nz, int *N, int *M, hullmi_stats *s
     const int nlow = w.ctl[kCtlOverflowLow];
     unsigned long long vl = 0, vh = 0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        const int32_t *q = w.q + 6 * (size_t)w.items[start + t];
+        const int32_t *q = w.rec + 6 * (size_t)(start + t);
         const bool high = t >= nlow;
         GlobalAcc3 acc{high ? M : N};
         const int v = walk_line(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, nz, acc);

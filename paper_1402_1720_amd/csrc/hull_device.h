@@ -48,17 +48,16 @@ __device__ __forceinline__ int quantize_point(float c, float s, float x, float y
     return kGeoOk;
 }
 
-// floor(a / b) for b > 0: an FP64 estimate corrected with exact products
-// (|a| < 2^56, b < 2^38, so the estimate is off by at most one).
-__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b)
+// floor(a / b) for b > 0 when the quotient is known to satisfy |a / b| < 2^12:
+// an FP32 estimate (relative error a few 2^-24, so within 2^-10 of a / b) is
+// off by at most one after flooring, and two exact integer comparisons fix it.
+__device__ __forceinline__ int64_t floor_div_small(int64_t a, int64_t b)
 {
-    int64_t q = (int64_t)floor((double)a / (double)b);
+    int64_t q = (int64_t)floorf((float)a * __builtin_amdgcn_rcpf((float)b));
     if (q * b > a) --q;
     if ((q + 1) * b <= a) ++q;
     return q;
 }
-
-__device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
 
 // Walk state after set-up: the first voxel of A_i and, per axis, the next
 // crossing written as pairwise decision variables.
@@ -121,10 +120,15 @@ __device__ __forceinline__ bool walk_init(int qix, int qiy, int qiz, int qox, in
         } else if (D[b] == 0) {
             c[b] = P[b] >> 10;
         } else {
+            // c = floor(num / den), or ceil(num / den) - 1 for a decreasing axis
+            // when a decreasing axis decides the entry; checked against [0, n)
+            // before dividing (den > 0), so the quotient is small
             const int64_t num = P[b] * aw + D[b] * ew;
-            c[b] = (gw && D[b] < 0) ? ceil_div(num, den) - 1 : floor_div(num, den);
+            const bool up = gw && D[b] < 0;
+            if (up ? (num <= 0 || num > (int64_t)n[b] * den) : (num < 0 || num >= (int64_t)n[b] * den))
+                return false;
+            c[b] = up ? -floor_div_small(-num, den) - 1 : floor_div_small(num, den);
         }
-        if (c[b] < 0 || c[b] >= n[b]) return false;
     }
     // next crossing per axis
     const int64_t ex = Dx > 0 ? (int64_t)kQ * (c[0] + 1) - Px : (Dx < 0 ? Px - (int64_t)kQ * c[0] : 1);
@@ -300,16 +304,69 @@ __device__ __forceinline__ void walk_slice(int qix, int qiy, int qiz, int qox, i
     else walk_slice_run<S, int64_t>(a, last, nx, ny, acc);
 }
 
+// z index of the first voxel of A_i (the cz of walk_init), or -1 when the line
+// misses the grid (exactly when walk_init returns false). The x and y indices
+// at the entry key are only range-checked, which needs no division: for
+// den > 0, floor(num / den) lies in [0, n) iff 0 <= num < n den, and
+// ceil(num / den) - 1 lies in [0, n) iff 0 < num <= n den.
+__device__ __forceinline__ int entry_z(int qix, int qiy, int qiz, int qox, int qoy, int qoz, int nx,
+                                       int ny, int nz)
+{
+    const int64_t P[3] = {qix, qiy, qiz};
+    const int64_t D[3] = {(int64_t)qox - qix, (int64_t)qoy - qiy, (int64_t)qoz - qiz};
+    const int n[3] = {nx, ny, nz};
+    int wa = -1;
+    int64_t ew = 0, aw = 1;
+    int gw = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int64_t L = (int64_t)kQ * n[b];
+        if (D[b] == 0) {
+            if (P[b] < 0 || P[b] >= L) return -1;   // a fixed axis outside the grid
+            continue;
+        }
+        // entry key of axis b: t = en / A, sigma = (D < 0); the latest one wins
+        const int64_t A = D[b] < 0 ? -D[b] : D[b];
+        const int64_t en = D[b] > 0 ? -P[b] : P[b] - L;
+        const int g = D[b] < 0;
+        if (wa >= 0) {
+            const int64_t l = en * aw, r = ew * A;
+            if (!(l > r || (l == r && g > gw))) continue;
+        }
+        wa = b; ew = en; aw = A; gw = g;
+    }
+    const int64_t den = (int64_t)kQ * aw;
+    int cz = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        int64_t c;
+        if (b == wa) {
+            c = D[b] > 0 ? 0 : n[b] - 1;
+        } else if (D[b] == 0) {
+            c = P[b] >> 10;
+        } else {
+            const int64_t num = P[b] * aw + D[b] * ew;
+            const bool up = gw && D[b] < 0;   // the ceiling form of walk_init
+            if (up ? (num <= 0 || num > (int64_t)n[b] * den) : (num < 0 || num >= (int64_t)n[b] * den))
+                return -1;
+            c = b == 2 ? (up ? -floor_div_small(-num, den) - 1 : floor_div_small(num, den)) : 0;
+        }
+        if (b == 2) cz = (int)c;
+    }
+    return cz;
+}
+
 // z-index range of A_i over the whole grid: the first voxel of the line and of
 // the reversed line. Returns false when the line misses the grid.
 __device__ __forceinline__ bool line_z_range(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
                                              int nx, int ny, int nz, int &k0, int &k1)
 {
-    WalkInit a, b;
-    if (!walk_init(qix, qiy, qiz, qox, qoy, qoz, nx, ny, nz, a)) return false;
-    if (!walk_init(qox, qoy, qoz, qix, qiy, qiz, nx, ny, nz, b)) return false;
-    k0 = min(a.cz, b.cz);
-    k1 = max(a.cz, b.cz);
+    const int a = entry_z(qix, qiy, qiz, qox, qoy, qoz, nx, ny, nz);
+    if (a < 0) return false;
+    const int b = entry_z(qox, qoy, qoz, qix, qiy, qiz, nx, ny, nz);
+    if (b < 0) return false;
+    k0 = min(a, b);
+    k1 = max(a, b);
     return true;
 }
 

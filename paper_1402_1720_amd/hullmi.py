@@ -52,6 +52,46 @@ class hullmi_fbp_params(ctypes.Structure):
                 ("filter", ctypes.c_int32), ("threshold", ctypes.c_float)]
 
 
+class hullmi_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n_low", "n_high", "n_skipped", "n_missed_grid",
+                                               "n_visits_low", "n_visits_high")]
+
+
+_OUT_FIELDS = [("N", ctypes.c_void_p), ("M", ctypes.c_void_p), ("sc_mask", ctypes.c_void_p),
+               ("msc_mask", ctypes.c_void_p), ("sm_mask", ctypes.c_void_p),
+               ("image", ctypes.c_void_p), ("fbp_mask", ctypes.c_void_p)]
+
+
+class hullmi_job(ctypes.Structure):
+    _fields_ = ([("op", ctypes.c_int32), ("flags", ctypes.c_uint32), ("hist", hullmi_histories),
+                 ("grid", hullmi_grid), ("params", hullmi_params), ("fbp", hullmi_fbp_params)]
+                + _OUT_FIELDS + [("stats", ctypes.c_void_p)])
+
+
+class hullmi_tuning(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("walk_blocks", ctypes.c_int32)]
+
+
+class hullmi_request(ctypes.Structure):
+    _fields_ = ([("op", ctypes.c_int32), ("hist", hullmi_histories), ("grid", hullmi_grid),
+                 ("params", hullmi_params), ("fbp", hullmi_fbp_params)] + _OUT_FIELDS)
+
+
+class hullmi_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("stats", hullmi_stats),
+                ("t_arrive_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("device_ms", ctypes.c_float),
+                ("h2d_ms", ctypes.c_float), ("compute_ms", ctypes.c_float),
+                ("d2h_ms", ctypes.c_float)]
+
+
+class hullmi_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "queued",
+                                               "running", "histories_done")] + \
+               [(k, ctypes.c_uint64) for k in ("bytes_budget", "bytes_in_use", "bytes_peak")]
+
+
 # every symbol the header declares, with its ctypes signature
 _P, _I32, _I64, _U32, _F, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                  ctypes.c_float, ctypes.c_size_t)
@@ -68,6 +108,17 @@ SIGNATURES = {
     "hull_fbp": ([_P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_count_lines": ([_P, _P, _I64, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_quantize": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "hull_footprint_bytes": ([ctypes.c_int, _P, _I64, _P], _SZ),
+    "hull_batch_plan": ([_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "hull_batch_launch": ([_P, _P], ctypes.c_int),
+    "hull_batch_tuning": ([_P, _P], ctypes.c_int),
+    "hull_batch_destroy": ([_P], ctypes.c_int),
+    "hull_server_create": ([_SZ, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
+                           ctypes.c_int),
+    "hull_server_submit": ([_P, _P, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "hull_server_wait": ([_P, ctypes.c_uint64, _P, _I64], ctypes.c_int),
+    "hull_server_stats": ([_P, _P], ctypes.c_int),
+    "hull_server_destroy": ([_P], ctypes.c_int),
 }
 
 _lib_handle = None
@@ -321,3 +372,162 @@ def hull_quantize(hist: Histories, grid, status: torch.Tensor, q_in: torch.Tenso
                              _dev_ptr(q_in, torch.int32, 3 * n, "q_in", d),
                              _dev_ptr(q_out, torch.int32, 3 * n, "q_out", d), _stream(stream))
     _check(rc, "hull_quantize")
+
+
+def hull_footprint_bytes(op: int, grid, n: int, fbp: Optional[hullmi_fbp_params] = None) -> int:
+    g = make_grid(grid)
+    r = lib().hull_footprint_bytes(int(op), ctypes.byref(g), int(n),
+                                   ctypes.byref(fbp) if fbp is not None else None)
+    if r == ctypes.c_size_t(-1).value:
+        raise HullError(HULL_EINVAL, "hull_footprint_bytes")
+    return int(r)
+
+
+# ---------------------------------------------------------------------------
+# batches
+
+_OP_OUTPUTS = {
+    HULL_OP_SC: ("N", "sc_mask"), HULL_OP_MSC: ("N", "msc_mask"), HULL_OP_SM: ("M", "sm_mask"),
+    HULL_OP_ALL: ("N", "M", "sc_mask", "msc_mask", "sm_mask"), HULL_OP_FBP: ("image", "fbp_mask"),
+}
+_OUT_DTYPES = {"N": torch.int32, "M": torch.int32, "sc_mask": torch.uint8,
+               "msc_mask": torch.uint8, "sm_mask": torch.uint8, "image": torch.float32,
+               "fbp_mask": torch.uint8}
+
+
+def make_job(op: int, hist: Histories, grid, params: Optional[hullmi_params] = None,
+             fbp: Optional[hullmi_fbp_params] = None, flags: int = 0, stats=None,
+             **outputs) -> hullmi_job:
+    """``hullmi_job`` for one scan; outputs are device tensors named as the
+    struct fields (N, M, sc_mask, msc_mask, sm_mask, image, fbp_mask)."""
+    g = make_grid(grid)
+    V = _voxels(g)
+    j = hullmi_job()
+    j.op, j.flags, j.hist, j.grid = int(op), int(flags), hist.c, g
+    j.params = params if params is not None else make_params()
+    if fbp is not None:
+        j.fbp = fbp
+    for k, t in outputs.items():
+        if k not in _OUT_DTYPES:
+            raise ValueError(f"unknown output {k}")
+        p = _dev_ptr(t, _OUT_DTYPES[k], V, k, hist.device)
+        setattr(j, k, p.value if p is not None else None)
+    sp = _stats_ptr(stats)
+    j.stats = sp.value if sp is not None else None
+    return j
+
+
+class BatchPlan:
+    """``hull_batch_plan`` over jobs; keeps the tensors the jobs point to
+    alive as long as the plan."""
+
+    def __init__(self, jobs: Sequence[hullmi_job], keep=(), tuning: Optional[hullmi_tuning] = None):
+        self._keep = list(keep)
+        arr = (hullmi_job * max(1, len(jobs)))(*jobs)
+        h = ctypes.c_void_p()
+        rc = lib().hull_batch_plan(arr, len(jobs), ctypes.byref(tuning) if tuning else None,
+                                   ctypes.byref(h))
+        _check(rc, "hull_batch_plan")
+        self._h = h
+
+    @property
+    def tuning(self) -> hullmi_tuning:
+        t = hullmi_tuning()
+        _check(lib().hull_batch_tuning(self._h, ctypes.byref(t)), "hull_batch_tuning")
+        return t
+
+    def launch(self, stream=None) -> None:
+        _check(lib().hull_batch_launch(self._h, _stream(stream)), "hull_batch_launch")
+
+    def close(self) -> None:
+        if self._h:
+            lib().hull_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# serving
+
+def _host_ptr(a, dtype, numel, name):
+    import numpy as np
+    if a is None:
+        return None
+    if not isinstance(a, np.ndarray) or a.dtype != dtype or not a.flags["C_CONTIGUOUS"]:
+        raise ValueError(f"{name} must be a C-contiguous numpy array of {dtype}")
+    if numel is not None and a.size != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {a.size}")
+    return a.ctypes.data
+
+
+class Server:
+    """``hull_server_*``: host histories in, host masks out. Submitted arrays
+    are kept alive until their ticket has been waited for."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 4, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().hull_server_create(int(hbm_budget), int(max_slots), int(device),
+                                        ctypes.byref(h)), "hull_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, op: int, hist: Dict[str, "np.ndarray"], grid,
+               params: Optional[hullmi_params] = None, fbp: Optional[hullmi_fbp_params] = None,
+               **outputs) -> int:
+        """Queues one request; outputs are host numpy arrays named as the
+        struct fields. Returns the ticket."""
+        import numpy as np
+        g = make_grid(grid)
+        V = _voxels(g)
+        n = int(hist["wepl"].size)
+        r = hullmi_request()
+        r.op, r.grid = int(op), g
+        r.hist = hullmi_histories(*[_host_ptr(hist[k], np.float32, n, k) if n else None
+                                    for k in FIELDS], n)
+        r.params = params if params is not None else make_params()
+        if fbp is not None:
+            r.fbp = fbp
+        np_types = {torch.int32: np.int32, torch.uint8: np.uint8, torch.float32: np.float32}
+        for k, a in outputs.items():
+            if k not in _OUT_DTYPES:
+                raise ValueError(f"unknown output {k}")
+            setattr(r, k, _host_ptr(a, np_types[_OUT_DTYPES[k]], V, k))
+        t = ctypes.c_uint64()
+        _check(lib().hull_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)),
+               "hull_server_submit")
+        self._keep[t.value] = (hist, outputs)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> Optional[Dict]:
+        """Result of a ticket as a dict, or None on time-out."""
+        res = hullmi_result()
+        rc = lib().hull_server_wait(self._h, int(ticket), ctypes.byref(res), int(timeout_us))
+        if rc == HULL_ETIMEDOUT:
+            return None
+        _check(rc, "hull_server_wait")
+        self._keep.pop(int(ticket), None)
+        out = {k: getattr(res, k) for k, _ in hullmi_result._fields_ if k != "stats"}
+        out["stats"] = {k: getattr(res.stats, k) for k, _ in hullmi_stats._fields_}
+        return out
+
+    def stats(self) -> Dict[str, int]:
+        st = hullmi_server_stats()
+        _check(lib().hull_server_stats(self._h, ctypes.byref(st)), "hull_server_stats")
+        return {k: int(getattr(st, k)) for k, _ in hullmi_server_stats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            lib().hull_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -124,3 +124,74 @@ def test_binding_checks_tensors_before_calling():
     import torch
     with pytest.raises(ValueError):
         H.Histories({k: torch.zeros(4) for k in H.FIELDS})   # host tensors
+
+
+def test_footprint_counts_inputs_outputs_and_workspace():
+    g = _grid()
+    V = 8 * 8 * 4
+    n = 1000
+    al = lambda b: (b + 255) // 256 * 256
+    for op, outs in ((H.HULL_OP_SC, [4 * V, V]), (H.HULL_OP_MSC, [4 * V, V]),
+                     (H.HULL_OP_SM, [4 * V, V]), (H.HULL_OP_ALL, [4 * V, 4 * V, V, V, V])):
+        ws = H.hull_workspace_bytes(op, g, n)
+        want = 8 * al(4 * n) + sum(al(b) for b in outs) + al(48) + al(ws)
+        assert H.hull_footprint_bytes(op, g, n) == want, op
+    f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
+    ws = H.hull_workspace_bytes(H.HULL_OP_FBP, g, n, f)
+    assert H.hull_footprint_bytes(H.HULL_OP_FBP, g, n, f) == \
+        8 * al(4 * n) + al(4 * V) + al(V) + al(48) + al(ws)
+    for bad in ((H.HULL_OP_COUNT_LINES, g, n), (H.HULL_OP_SC, g, -1), (H.HULL_OP_SC, g, 2 ** 31),
+                (H.HULL_OP_SC, _grid(ny=0), n), (H.HULL_OP_FBP, g, n)):
+        with pytest.raises(H.HullError):
+            H.hull_footprint_bytes(*bad)
+
+
+def _job(**kw):
+    j = H.hullmi_job()
+    j.op = H.HULL_OP_SC
+    j.hist = _hist()
+    j.grid = _grid()
+    j.params = H.make_params()
+    j.N = FAKE.value
+    for k, v in kw.items():
+        setattr(j, k, v)
+    return j
+
+
+def test_batch_plan_rejects_bad_jobs_before_touching_the_device():
+    L = H.lib()
+    out = ctypes.c_void_p()
+    assert L.hull_batch_plan(None, 1, None, ctypes.byref(out)) == H.HULL_EINVAL
+    assert L.hull_batch_plan(None, -1, None, ctypes.byref(out)) == H.HULL_EINVAL
+    jobs = (H.hullmi_job * 2)(_job(), _job())
+    assert L.hull_batch_plan(jobs, 2, None, None) == H.HULL_EINVAL
+    bad = [_job(N=None), _job(op=9), _job(op=H.HULL_OP_SM), _job(grid=_grid(nx=0)),
+           _job(hist=_hist(null="wepl")), _job(op=H.HULL_OP_MSC, params=H.make_params(msc_n_t=0)),
+           _job(op=H.HULL_OP_FBP, image=FAKE.value)]
+    for b in bad:
+        arr = (H.hullmi_job * 2)(_job(), b)
+        assert L.hull_batch_plan(arr, 2, None, ctypes.byref(out)) == H.HULL_EINVAL
+        assert out.value is None
+    # bad tuning
+    for t in (H.hullmi_tuning(0, 1, 0), H.hullmi_tuning(17, 1, 0), H.hullmi_tuning(2, 2, 0),
+              H.hullmi_tuning(2, 1, -1)):
+        assert L.hull_batch_plan(jobs, 2, ctypes.byref(t), ctypes.byref(out)) == H.HULL_EINVAL
+    assert L.hull_batch_launch(None, None) == H.HULL_EINVAL
+    assert L.hull_batch_tuning(None, None) == H.HULL_EINVAL
+    assert L.hull_batch_destroy(None) == H.HULL_OK
+
+
+def test_server_argument_checks():
+    L = H.lib()
+    out = ctypes.c_void_p()
+    assert L.hull_server_create(0, 4, 0, ctypes.byref(out)) == H.HULL_EINVAL
+    assert L.hull_server_create(1 << 30, 0, 0, ctypes.byref(out)) == H.HULL_EINVAL
+    assert L.hull_server_create(1 << 30, 65, 0, ctypes.byref(out)) == H.HULL_EINVAL
+    assert L.hull_server_create(1 << 30, 4, -1, ctypes.byref(out)) == H.HULL_EINVAL
+    assert L.hull_server_create(1 << 30, 4, 0, None) == H.HULL_EINVAL
+    t = ctypes.c_uint64()
+    r = H.hullmi_request()
+    assert L.hull_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == H.HULL_EINVAL
+    assert L.hull_server_wait(None, 1, None, 0) == H.HULL_EINVAL
+    assert L.hull_server_stats(None, None) == H.HULL_EINVAL
+    assert L.hull_server_destroy(None) == H.HULL_OK
