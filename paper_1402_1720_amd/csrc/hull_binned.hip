@@ -102,21 +102,44 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
     uint32_t trig_bits = 0x7fc00001u;   // a NaN: finite angles never match it
     float tc = 1.0f, ts = 0.0f;
     const int64_t base = (int64_t)blockIdx.x * kHistPerBlock;
+    // two-stage prefetch: the WEPL two histories ahead, and the geometry of the
+    // next history when its WEPL puts it in a class being counted (a wave with
+    // no such lane skips those loads)
+    auto in_class = [&](float wv) {
+        return isfinite(wv) && ((use_low && wv < e_low) || (use_high && wv > e_high));
+    };
+    auto hist_at = [&](int r) { return base + (int64_t)r * kBinThreads + threadIdx.x; };
+    struct Geo { float xi, yi, zi, xo, yo, zo, a; };
+    auto fetch_geo = [&](int64_t i, Geo &f) {
+        f.xi = h.x_in[i]; f.yi = h.y_in[i]; f.zi = h.z_in[i];
+        f.xo = h.x_out[i]; f.yo = h.y_out[i]; f.zo = h.z_out[i]; f.a = h.angle_deg[i];
+    };
+    float w_next = 0.0f, w_next2 = 0.0f;
+    Geo g_next{};
+    if (hist_at(0) < nb) {
+        w_next = h.wepl[h0 + hist_at(0)];
+        if (in_class(w_next)) fetch_geo(h0 + hist_at(0), g_next);
+    }
+    if (kHistPerThread > 1 && hist_at(1) < nb) w_next2 = h.wepl[h0 + hist_at(1)];
     for (int r = 0; r < kHistPerThread; ++r) {
-        const int64_t j = base + (int64_t)r * kBinThreads + threadIdx.x;
+        const int64_t j = hist_at(r);
         if (j >= nb) break;
-        const int64_t i = h0 + j;
+        const float wv = w_next;
+        const Geo cf = g_next;
+        w_next = w_next2;
+        if (r + 1 < kHistPerThread && hist_at(r + 1) < nb && in_class(w_next))
+            fetch_geo(h0 + hist_at(r + 1), g_next);
+        if (r + 2 < kHistPerThread && hist_at(r + 2) < nb) w_next2 = h.wepl[h0 + hist_at(r + 2)];
         uint32_t meta = 0;
-        const float wv = h.wepl[i];
         if (!isfinite(wv)) {
             ++nsk;
         } else {
             const bool low = use_low && wv < e_low;
             const bool high = use_high && wv > e_high;
             if (low || high) {
-                const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
-                const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
-                const float a = h.angle_deg[i];
+                const float xi = cf.xi, yi = cf.yi, zi = cf.zi;
+                const float xo = cf.xo, yo = cf.yo, zo = cf.zo;
+                const float a = cf.a;
                 int q[6];
                 int stg = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) &&
                            isfinite(yo) && isfinite(zo) && isfinite(a))
@@ -313,26 +336,40 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
         cur[b] = w.sub_start[b] + w.blk[(int64_t)b * w.nblk + blockIdx.x];
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kHistPerBlock;
+    const int64_t base = (int64_t)blockIdx.x * kHistPerBlock + threadIdx.x;
+    // the next history's meta word, length classes and endpoint record are
+    // loaded (independently of each other) while the current one is placed;
+    // the record of an unclassified history is read but not used
+    struct Next { uint32_t m, lp; int2 a, b, c; };
+    auto fetch = [&](int r, Next &x) {
+        const int64_t j = base + (int64_t)r * kBinThreads;
+        x.m = 0;
+        if (r < kHistPerThread && j < nb) {
+            x.m = w.meta[j];
+            x.lp = w.lpack[j];
+            const int2 *src = reinterpret_cast<const int2 *>(w.q + 6 * j);
+            x.a = src[0]; x.b = src[1]; x.c = src[2];
+        }
+    };
+    Next nx;
+    fetch(0, nx);
     for (int r = 0; r < kHistPerThread; ++r) {
-        const int64_t j = base + (int64_t)r * kBinThreads + threadIdx.x;
-        if (j >= nb) break;
-        const uint32_t m = w.meta[j];
+        if (base + (int64_t)r * kBinThreads >= nb) break;
+        const Next cu = nx;
+        fetch(r + 1, nx);
+        const uint32_t m = cu.m;
         if (!(m & kMetaValid)) continue;
         const int cls = (m & kMetaHigh) ? 1 : 0;
-        const int2 *src = reinterpret_cast<const int2 *>(w.q + 6 * j);
-        const int2 a = src[0], b = src[1], c = src[2];
         auto put = [&](uint32_t p) {
             int2 *dst = reinterpret_cast<int2 *>(w.rec + 6 * (size_t)p);
-            dst[0] = a; dst[1] = b; dst[2] = c;
+            dst[0] = cu.a; dst[1] = cu.b; dst[2] = cu.c;
         };
         if (m & kMetaOverflow) {
             put(atomicAdd(&cur[w.nsub - 2 + cls], 1u));
         } else {
             const int k0 = (int)(m & 0xfffu), ns = (int)((m >> 12) & 0xfffu);
-            const uint32_t lp = w.lpack[j];
             for (int k = k0; k < k0 + ns; ++k) {
-                const int lc = (int)((lp >> (4 * (k - k0))) & 0xfu);
+                const int lc = (int)((cu.lp >> (4 * (k - k0))) & 0xfu);
                 put(atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u));
             }
         }
@@ -411,7 +448,7 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
 __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N, int *M, hullmi_stats *st)
 {
     __shared__ uint32_t slots[256];
-    __shared__ int nslots, more;
+    __shared__ int r0;
     __shared__ unsigned long long red[16];
     const int t = blockIdx.y;
     const int cls = t / w.nz, k = t % w.nz;
@@ -420,28 +457,30 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N
     const int nranges = w.ctl[kCtlRanges];
     const int wd = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t lo = 0, hi = 0;
-    // ranges overlapping [ta, tb), 256 at a time
-    int r = count_le(w.range_start, 0, nranges + 1, ta) - 1;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int n = 0;
-            while (n < 256 && r < nranges && w.range_start[r] < tb) {
-                const uint32_t a = max(w.range_start[r], ta), b = min(w.range_start[r + 1], tb);
-                if (a < b) slots[n++] = (uint32_t)slot_of(w, nranges, a);
-                ++r;
-            }
-            nslots = n;
-            more = (r < nranges && w.range_start[r] < tb) ? 1 : 0;
+    if (threadIdx.x == 0) r0 = count_le(w.range_start, 0, nranges + 1, ta) - 1;
+    __syncthreads();
+    // ranges overlapping [ta, tb), 256 at a time, one per thread: the ranges
+    // that start before tb are a prefix of them (starts never decrease)
+    for (int rb = r0;; rb += 256) {
+        const int r = rb + (int)threadIdx.x;
+        const bool in = r < nranges && w.range_start[r] < tb;
+        uint32_t sl = 0xffffffffu;   // empty segment: nothing to add
+        if (in) {
+            const uint32_t a = max(w.range_start[r], ta), b = min(w.range_start[r + 1], tb);
+            if (a < b) sl = (uint32_t)slot_of(w, nranges, a);
         }
-        __syncthreads();
+        slots[threadIdx.x] = sl;
+        const int n = __syncthreads_count(in);
         if (wd < w.tile_words)
-            for (int s = 0; s < nslots; ++s) {
-                const uint32_t v = w.partial[(int64_t)slots[s] * w.tile_words + wd];
+            for (int s = 0; s < n; ++s) {
+                const uint32_t q = slots[s];
+                if (q == 0xffffffffu) continue;
+                const uint32_t v = w.partial[(int64_t)q * w.tile_words + wd];
                 lo += v & 0xffffu;
                 hi += v >> 16;
             }
-        if (!more) break;   // r advances in thread 0 only
+        if (n < 256) break;   // uniform: n is the same in every thread
+        __syncthreads();      // slots are rewritten in the next round
     }
     int *dst = cls ? M : N;
     if (wd < w.tile_words) {

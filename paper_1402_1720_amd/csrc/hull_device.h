@@ -227,11 +227,12 @@ __device__ __forceinline__ void walk_slice_run(const WalkInit &a, int last, int 
 // (the compiler keeps the loop guard and the any-lane test in vector
 // registers; here they are scalar): per step 12 VALU instructions and one
 // ds_add_u32. Lanes leave the exec mask when they have visited `last`; the
-// loop also ends after nx + ny rounds. Only LDS is touched: `base` is the LDS
-// byte address of the tile, `off` the byte offset 2 * voxel of the counter.
+// loop also ends after maxit rounds. Only LDS is touched: `off` and `last` are
+// LDS byte addresses of 16-bit counters (tile base + 2 * voxel, the base a
+// multiple of 4), so the word is off & ~3 and the half is bit 1 of off.
 __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t last,
                                                  int32_t incx, int32_t incy, int32_t ox,
-                                                 int32_t oy, uint32_t base, int32_t maxit)
+                                                 int32_t oy, int32_t maxit)
 {
     const int32_t incxy = incx + incy, oxy = ox + oy;
     int32_t t0, t1, t2;
@@ -247,7 +248,6 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
         "v_cmp_ne_u32 vcc, %[off], %[last]\n"
         "v_and_b32 %[t0], -4, %[off]\n"
         "v_bfe_u32 %[t1], %[off], 1, 1\n"
-        "v_add_u32 %[t0], %[base], %[t0]\n"
         "v_cndmask_b32 %[t2], %[incy], %[incxy], %[stie]\n"
         "v_cndmask_b32 %[t2], %[t2], %[incx], %[sbx]\n"
         "v_add_u32 %[d], %[d], %[t2]\n"
@@ -266,7 +266,7 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
         : [d] "+v"(d), [off] "+v"(off), [it] "+s"(it), [t0] "=&v"(t0), [t1] "=&v"(t1),
           [t2] "=&v"(t2), [save] "=&s"(save), [sbx] "=&s"(sbx), [stie] "=&s"(stie)
         : [last] "v"(last), [incx] "v"(incx), [incy] "v"(incy), [incxy] "v"(incxy),
-          [ox] "v"(ox), [oy] "v"(oy), [oxy] "v"(oxy), [base] "v"(base), [k16] "s"(65535)
+          [ox] "v"(ox), [oy] "v"(oy), [oxy] "v"(oxy), [k16] "s"(65535)
         : "vcc", "scc", "memory");
 }
 
@@ -284,8 +284,9 @@ __device__ __forceinline__ void walk_slice_tile16(int qix, int qiy, int qiz, int
     if (!walk_init(qox, qoy, qoz - zs, qix, qiy, qiz - zs, nx, ny, 1, b)) return;
     const int last = 2 * (b.cx + nx * b.cy);
     if (max(a.Ax, a.Ay) < (int64_t(1) << 19)) {
-        walk_slice_lds16((int32_t)a.dxy, 2 * (a.cx + nx * a.cy), last, (int32_t)(2048 * a.Ay),
-                         (int32_t)(-2048 * a.Ax), 2 * a.sx, 2 * a.sy * nx, base, nx + ny);
+        walk_slice_lds16((int32_t)a.dxy, (int32_t)base + 2 * (a.cx + nx * a.cy),
+                         (int32_t)base + last, (int32_t)(2048 * a.Ay), (int32_t)(-2048 * a.Ax),
+                         2 * a.sx, 2 * a.sy * nx, nx + ny);
     } else {
         walk_slice_run<2, int64_t>(a, last, nx, ny, acc);
     }
