@@ -408,12 +408,23 @@ int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     fill_u64(w.sum, 0ull, nb, s);
     fill_u32(w.cnt, 0u, nb, s);
     if (hist->n > 0) {
+        // one or two LDS copies of a detector plane (12 bytes per bin each);
+        // chunks so that every resident block gets one
         const size_t plane_lds = (size_t)p.nu * p.nv * 12;
-        if (plane_lds <= allow_max_lds(reinterpret_cast<const void *>(k_fbp_bin_lds),
-                                       dev_props().max_lds)) {
-            const int64_t chunk = 32768;
-            k_fbp_bin_lds<<<(unsigned)((hist->n + chunk - 1) / chunk), kBlock, plane_lds, s>>>(
-                *hist, p, w.sum, w.cnt, chunk);
+        const DevProps dp = dev_props();
+        const size_t lim = allow_max_lds(reinterpret_cast<const void *>(k_fbp_bin_lds), dp.max_lds);
+        const int nplanes = 2 * plane_lds <= lim ? 2 : (plane_lds <= lim ? 1 : 0);
+        if (nplanes > 0) {
+            const size_t lds = nplanes * plane_lds;
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fbp_bin_lds, kFbpBinThreads,
+                                                             lds) != hipSuccess || occ < 1)
+                occ = 1;
+            const int64_t want = std::min<int64_t>((int64_t)dp.cus * occ,
+                                                   (hist->n + kFbpBinThreads - 1) / kFbpBinThreads);
+            const int64_t chunk = (hist->n + want - 1) / want;
+            k_fbp_bin_lds<<<(unsigned)((hist->n + chunk - 1) / chunk), kFbpBinThreads, lds, s>>>(
+                *hist, p, w.sum, w.cnt, chunk, nplanes);
         } else {
             k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
         }

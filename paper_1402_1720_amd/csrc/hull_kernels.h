@@ -37,8 +37,9 @@ __global__ void k_seg_slope_argmax(const int *M, unsigned long long *out, int nx
 __global__ void k_sm_mask(const int *M, uint8_t *mask, int64_t V, int64_t seg_len, int mode,
                           int num, int den, const unsigned long long *seg);
 __global__ void k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt);
+constexpr int kFbpBinThreads = 1024;   // block of the LDS-binned FDK histogram
 __global__ void k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt,
-                              int64_t chunk);
+                              int64_t chunk, int nplanes);
 __global__ void k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p);
 __global__ void k_fbp_trig(float2 *cs, FbpDev p);
 __global__ void k_fbp_backproject(const float *q, const float2 *cs, FbpDev p, FbpGridDev g,

@@ -277,12 +277,10 @@ __global__ void k_sm_mask(const int *M, uint8_t *mask, int64_t V, int64_t seg_le
 // Where a history's line crosses x = 0, decided in FP32: gantry angle bin k,
 // detector bin (iu, iv) and the WEPL in fixed point (2^-16 mm). False when the
 // history is not binned.
-__device__ __forceinline__ bool fbp_locate(const hullmi_histories &h, int64_t i, const FbpDev &p,
-                                           int &k, int &iu, int &iv, long long &fx)
+__device__ __forceinline__ bool fbp_locate_vals(float xi, float yi, float zi, float xo, float yo,
+                                                float zo, float a, float w, const FbpDev &p, int &k,
+                                                int &iu, int &iv, long long &fx)
 {
-    const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
-    const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
-    const float a = h.angle_deg[i], w = h.wepl[i];
     if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
           isfinite(zo) && isfinite(a) && isfinite(w)))
         return false;
@@ -304,6 +302,13 @@ __device__ __forceinline__ bool fbp_locate(const hullmi_histories &h, int64_t i,
     iv = (int)floorf(fv);
     fx = llrint((double)w * 65536.0);
     return true;
+}
+
+__device__ __forceinline__ bool fbp_locate(const hullmi_histories &h, int64_t i, const FbpDev &p,
+                                           int &k, int &iu, int &iv, long long &fx)
+{
+    return fbp_locate_vals(h.x_in[i], h.y_in[i], h.z_in[i], h.x_out[i], h.y_out[i], h.z_out[i],
+                           h.angle_deg[i], h.wepl[i], p, k, iu, iv, fx);
 }
 
 // Angle bin of a history from its angle alone (-1 when it cannot be binned).
@@ -332,38 +337,50 @@ k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt)
     atomicAdd(cnt + b, 1u);
 }
 
-// The same binning for a chunk of consecutive histories per block: the chunk's
-// first angle bin (histories arrive angle by angle) is accumulated in an LDS
-// copy of its detector plane and added to the global sums once; histories of
-// other angle bins in the chunk go straight to the global sums. Same fixed
-// point, so the sums are identical to k_fbp_bin's.
-__global__ void __launch_bounds__(256)
-k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt, int64_t chunk)
+// The same binning for a chunk of consecutive histories per block. Histories
+// arrive angle by angle, so the angle bins of a chunk's first and last history
+// usually hold all of it: each gets an LDS copy of the detector plane (sums and
+// counts, nplanes = 2, or only the first with nplanes = 1), added to the global
+// sums once; histories of any other angle bin go straight to the global sums.
+// The next history's fields are loaded while the current one is binned. Same
+// fixed point, so the sums are identical to k_fbp_bin's.
+__global__ void __launch_bounds__(kFbpBinThreads)
+k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt, int64_t chunk,
+              int nplanes)
 {
-    extern __shared__ unsigned long long lsum[];   // plane sums, then plane counts (u32)
+    extern __shared__ unsigned long long lsum[];   // nplanes plane sums, then nplanes plane counts
     const int plane = p.nu * p.nv;
-    unsigned *lcnt = reinterpret_cast<unsigned *>(lsum + plane);
-    __shared__ int kref;
+    unsigned *lcnt = reinterpret_cast<unsigned *>(lsum + (int64_t)nplanes * plane);
     const int64_t base = (int64_t)blockIdx.x * chunk;
     const int64_t end = min(base + chunk, h.n);
-    if (threadIdx.x == 0) kref = 0x7fffffff;
-    for (int b = threadIdx.x; b < plane; b += blockDim.x) { lsum[b] = 0ull; lcnt[b] = 0u; }
+    if (base >= end) return;   // uniform across the block
+    for (int b = threadIdx.x; b < nplanes * plane; b += blockDim.x) { lsum[b] = 0ull; lcnt[b] = 0u; }
+    const int k0 = fbp_angle_bin(h.angle_deg[base], p);
+    int k1 = nplanes > 1 ? fbp_angle_bin(h.angle_deg[end - 1], p) : -1;
+    if (k1 == k0) k1 = -1;
     __syncthreads();
-    // the smallest angle bin of the chunk's first 256 histories
-    if (base + threadIdx.x < end) {
-        const int k = fbp_angle_bin(h.angle_deg[base + threadIdx.x], p);
-        if (k >= 0) atomicMin(&kref, k);
-    }
-    __syncthreads();
-    const int kr = kref;
+    struct F8 { float xi, yi, zi, xo, yo, zo, a, w; };
+    auto fetch = [&](int64_t i, F8 &f) {
+        if (i < end) {
+            f.xi = h.x_in[i]; f.yi = h.y_in[i]; f.zi = h.z_in[i];
+            f.xo = h.x_out[i]; f.yo = h.y_out[i]; f.zo = h.z_out[i];
+            f.a = h.angle_deg[i]; f.w = h.wepl[i];
+        }
+    };
+    F8 nf{};
+    fetch(base + threadIdx.x, nf);
     for (int64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+        const F8 f = nf;
+        fetch(i + blockDim.x, nf);
         int k, iu, iv;
         long long fx;
-        if (!fbp_locate(h, i, p, k, iu, iv, fx)) continue;
+        if (!fbp_locate_vals(f.xi, f.yi, f.zi, f.xo, f.yo, f.zo, f.a, f.w, p, k, iu, iv, fx))
+            continue;
         const int pb = iv * p.nu + iu;
-        if (k == kr) {
-            atomicAdd(&lsum[pb], (unsigned long long)fx);
-            atomicAdd(&lcnt[pb], 1u);
+        if (k == k0 || k == k1) {
+            const int lb = (k == k0 ? 0 : plane) + pb;
+            atomicAdd(&lsum[lb], (unsigned long long)fx);
+            atomicAdd(&lcnt[lb], 1u);
         } else {
             const int64_t b = (int64_t)k * plane + pb;
             atomicAdd(sum + b, (unsigned long long)fx);
@@ -371,12 +388,13 @@ k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *c
         }
     }
     __syncthreads();
-    if (kr == 0x7fffffff) return;
-    for (int b = threadIdx.x; b < plane; b += blockDim.x) {
+    for (int b = threadIdx.x; b < nplanes * plane; b += blockDim.x) {
+        const int kb = b < plane ? k0 : k1;
         const unsigned c = lcnt[b];
-        if (c) {
-            atomicAdd(sum + (int64_t)kr * plane + b, lsum[b]);
-            atomicAdd(cnt + (int64_t)kr * plane + b, c);
+        if (kb >= 0 && c) {
+            const int64_t g = (int64_t)kb * plane + (b < plane ? b : b - plane);
+            atomicAdd(sum + g, lsum[b]);
+            atomicAdd(cnt + g, c);
         }
     }
 }
