@@ -23,8 +23,6 @@ struct FbpGridDev {
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n);
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n);
-__global__ void k_walk_histories(hullmi_histories h, DevGrid g, float e_low, float e_high, int *N,
-                                 int *M, hullmi_stats *st);
 __global__ void k_walk_lines(const int *qin, const int *qout, int64_t n, int nx, int ny, int nz,
                              int *cnt, hullmi_stats *st);
 __global__ void k_quantize(hullmi_histories h, DevGrid g, int *status, int *qin, int *qout);

@@ -48,55 +48,6 @@ struct GlobalAcc {
     __device__ __forceinline__ void operator()(int off) const { atomicAdd(cnt + off, 1); }
 };
 
-// ---------------------------------------------------------------------------
-// classify -> geometry -> walk -> accumulate, one history per lane
-
-__global__ void __launch_bounds__(256)
-k_walk_histories(hullmi_histories h, DevGrid g, float e_low, float e_high, int *N, int *M,
-                 hullmi_stats *st)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long nl = 0, nh = 0, nsk = 0, nmi = 0, vl = 0, vh = 0;
-    if (i < h.n) {
-        const float w = h.wepl[i];
-        if (!isfinite(w)) {
-            nsk = 1;
-        } else {
-            const bool low = N != nullptr && w < e_low;
-            const bool high = M != nullptr && w > e_high;
-            if (low || high) {
-                const float xi = h.x_in[i], yi = h.y_in[i], zi = h.z_in[i];
-                const float xo = h.x_out[i], yo = h.y_out[i], zo = h.z_out[i];
-                const float a = h.angle_deg[i];
-                int qi[3], qo[3];
-                int stg = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) &&
-                           isfinite(yo) && isfinite(zo) && isfinite(a))
-                              ? kGeoOk
-                              : kGeoNonFinite;
-                if (stg == kGeoOk) {
-                    float c, s;
-                    deg_cos_sin(a, c, s);
-                    stg = quantize_point(c, s, xi, yi, zi, g, qi[0], qi[1], qi[2]);
-                    if (stg == kGeoOk) stg = quantize_point(c, s, xo, yo, zo, g, qo[0], qo[1], qo[2]);
-                    if (stg == kGeoOk && qi[0] == qo[0] && qi[1] == qo[1] && qi[2] == qo[2])
-                        stg = kGeoDegenerate;
-                }
-                if (stg != kGeoOk) {
-                    nsk = 1;
-                } else {
-                    GlobalAcc acc{low ? N : M};
-                    const int c = walk_line(qi[0], qi[1], qi[2], qo[0], qo[1], qo[2], g.nx, g.ny,
-                                            g.nz, acc);
-                    if (low) { nl = 1; vl = (unsigned long long)c; }
-                    else { nh = 1; vh = (unsigned long long)c; }
-                    nmi = c == 0;
-                }
-            }
-        }
-    }
-    if (st) flush_stats(st, nl, nh, nsk, nmi, vl, vh);
-}
-
 __global__ void __launch_bounds__(256)
 k_walk_lines(const int *qin, const int *qout, int64_t n, int nx, int ny, int nz, int *cnt,
              hullmi_stats *st)
