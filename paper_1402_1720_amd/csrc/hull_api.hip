@@ -212,10 +212,20 @@ struct FbpWs {
     float *q;
     size_t qn;
     float2 *cs;
+    int4 *fp;          // footprint of every (backprojection tile, angle)
     size_t bytes;
 };
 
-FbpWs fbp_ws_layout(const hullmi_fbp_params *p, void *base)
+// Tiles of the tiled backprojection (kBpTile x kBpTile columns x kFbpZ slices).
+inline int64_t bp_tiles(const hullmi_grid *g, int &ntx, int &nty, int &ntz)
+{
+    ntx = (g->nx + kBpTile - 1) / kBpTile;
+    nty = (g->ny + kBpTile - 1) / kBpTile;
+    ntz = (g->nz + 7) / 8;
+    return (int64_t)ntx * nty * ntz;
+}
+
+FbpWs fbp_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, void *base)
 {
     const size_t nb = (size_t)p->nu * p->nv * p->n_angles;
     FbpWs w;
@@ -227,6 +237,9 @@ FbpWs fbp_ws_layout(const hullmi_fbp_params *p, void *base)
     w.qn = (size_t)p->n_angles * (p->nv + 4) * (p->nu + 4);   // padded filtered projections
     off += align_up(w.qn * 4);
     w.cs = reinterpret_cast<float2 *>(b + off);              off += align_up((size_t)p->n_angles * 8);
+    int ntx, nty, ntz;
+    w.fp = reinterpret_cast<int4 *>(b + off);
+    off += align_up((size_t)bp_tiles(g, ntx, nty, ntz) * p->n_angles * sizeof(int4));
     w.bytes = off;
     return w;
 }
@@ -394,9 +407,9 @@ int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
              float *image, uint8_t *mask, void *ws, size_t ws_bytes, hipStream_t s)
 {
     if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image) return HULL_EINVAL;
-    const size_t need = fbp_ws_layout(fbp, nullptr).bytes;
+    const size_t need = fbp_ws_layout(fbp, grid, nullptr).bytes;
     if (!ws || ws_bytes < need) return HULL_ENOMEM;
-    FbpWs w = fbp_ws_layout(fbp, ws);
+    FbpWs w = fbp_ws_layout(fbp, grid, ws);
     FbpDev p;
     p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
     p.u0 = fbp->u0_mm; p.v0 = fbp->v0_mm;
@@ -435,8 +448,12 @@ int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
     FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
                   grid->x0, grid->y0, grid->z0};
-    const int64_t ncol = (int64_t)grid->nx * grid->ny * ((grid->nz + 7) / 8);
-    k_fbp_backproject<<<blocks_for(ncol), kBlock, 0, s>>>(w.q, w.cs, p, gd, image, mask);
+    int ntx, nty, ntz;
+    const int64_t ntiles = bp_tiles(grid, ntx, nty, ntz);
+    k_fbp_footprint<<<blocks_for(ntiles * p.n_angles), kBlock, 0, s>>>(w.cs, p, gd, w.fp, ntx, nty,
+                                                                       ntz);
+    k_fbp_backproject_tiles<<<(unsigned)ntiles, kBpTile * kBpTile, 0, s>>>(w.q, w.cs, w.fp, p, gd,
+                                                                          image, mask, ntx, nty);
     return launch_status();
 }
 
@@ -457,7 +474,7 @@ size_t ws_bytes_of(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_
         return counts_ws_bytes(grid, n) + sm_ws_bytes(grid);
     case HULL_OP_FBP:
         if (!grid_ok(grid) || !fbp_ok(fbp)) return (size_t)-1;
-        return fbp_ws_layout(fbp, nullptr).bytes;
+        return fbp_ws_layout(fbp, grid, nullptr).bytes;
     default:
         return (size_t)-1;
     }

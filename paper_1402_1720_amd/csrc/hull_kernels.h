@@ -40,7 +40,11 @@ __global__ void k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *
                               int64_t chunk, int nplanes);
 __global__ void k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p);
 __global__ void k_fbp_trig(float2 *cs, FbpDev p);
-__global__ void k_fbp_backproject(const float *q, const float2 *cs, FbpDev p, FbpGridDev g,
-                                  float *image, uint8_t *mask);
+constexpr int kBpTile = 16;      // columns per side of a tiled-backprojection block
+constexpr int kBpStage = 2048;   // floats of projection footprint staged in LDS
+__global__ void k_fbp_footprint(const float2 *cs, FbpDev p, FbpGridDev g, int4 *fp, int ntx,
+                                int nty, int ntz);
+__global__ void k_fbp_backproject_tiles(const float *q, const float2 *cs, const int4 *fp, FbpDev p,
+                                        FbpGridDev g, float *image, uint8_t *mask, int ntx, int nty);
 
 }  // namespace hullmi

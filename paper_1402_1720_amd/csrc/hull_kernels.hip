@@ -403,16 +403,114 @@ __global__ void k_fbp_trig(float2 *cs, FbpDev p)
 // that border samples zeros. Threshold fused.
 constexpr int kFbpZ = 8;
 
-__global__ void __launch_bounds__(256)
-k_fbp_backproject(const float *q, const float2 *cs, FbpDev p, FbpGridDev g, float *image,
-                  uint8_t *mask)
+// One (column, angle) term for kFbpZ slices: `sample(iv, iu, row)` returns the
+// padded projection values at row iv + 2 + row, bins iu + 2 and iu + 3, as a
+// float2 (left, right); the same arithmetic whether they come from LDS or
+// from global memory.
+template <class Sample>
+__device__ __forceinline__ void bp_term(float2 c, float xo, float yo, const float *zo, float *f,
+                                        const FbpDev &p, float D, float rD, Sample &&sample)
 {
-    const int ngz = (g.nz + kFbpZ - 1) / kFbpZ;
+    const float xl = c.x * xo - c.y * yo;
+    const float yl = c.y * xo + c.x * yo;
+    const float U = (D + xl) * rD;
+    if (!(U > 0.0f)) return;   // voxel at or behind the source plane
+    const float iU = __builtin_amdgcn_rcpf(U);
+    const float w2 = iU * iU;
+    const float fu = (yl * iU - p.u0) * p.rdu - 0.5f;
+    const float fu0 = floorf(fu);
+    const float au = fu - fu0;
+    const int iu0 = min(max((int)fmaxf(fminf(fu0, 1.0e8f), -1.0e8f), -2), p.nu);
+    const float fvs = iU * p.rdv;
+#pragma unroll
+    for (int z = 0; z < kFbpZ; ++z) {
+        const float fv = zo[z] * fvs - p.v0 * p.rdv - 0.5f;
+        const float fv0 = floorf(fv);
+        const float av = fv - fv0;
+        const int iv0 = min(max((int)fmaxf(fminf(fv0, 1.0e8f), -1.0e8f), -2), p.nv);
+        const float2 t = sample(iv0, iu0, 0), b = sample(iv0, iu0, 1);
+        const float top = t.x + au * (t.y - t.x);
+        const float bot = b.x + au * (b.y - b.x);
+        f[z] += (top + av * (bot - top)) * w2;
+    }
+}
+
+// The bin and row indices bp_term uses for one column at one angle: iu0 and
+// the range of iv0 over the slices z_lo .. z_hi; false behind the source.
+__device__ __forceinline__ bool bp_indices(float2 c, float xo, float yo, float z_lo, float z_hi,
+                                           const FbpDev &p, float D, float rD, int &iu0,
+                                           int &iv_min, int &iv_max)
+{
+    const float xl = c.x * xo - c.y * yo;
+    const float yl = c.y * xo + c.x * yo;
+    const float U = (D + xl) * rD;
+    if (!(U > 0.0f)) return false;
+    const float iU = __builtin_amdgcn_rcpf(U);
+    const float fu = (yl * iU - p.u0) * p.rdu - 0.5f;
+    iu0 = min(max((int)fmaxf(fminf(floorf(fu), 1.0e8f), -1.0e8f), -2), p.nu);
+    const float fvs = iU * p.rdv;
+    int a = min(max((int)fmaxf(fminf(floorf(z_lo * fvs - p.v0 * p.rdv - 0.5f), 1.0e8f), -1.0e8f), -2), p.nv);
+    int b = min(max((int)fmaxf(fminf(floorf(z_hi * fvs - p.v0 * p.rdv - 0.5f), 1.0e8f), -1.0e8f), -2), p.nv);
+    iv_min = min(a, b);
+    iv_max = max(a, b);
+    return true;
+}
+
+// Footprint on the padded projection of every (tile, angle) of the tiled
+// backprojection: bins [x, x + z) and rows [y, y + w) hold every sample the
+// tile's lanes take at that angle (extremes at the tile's corner columns and
+// end slices, widened by one bin and one row for rounding); z = 0 when a
+// corner lies at or behind the source (the tile then reads global memory).
+__global__ void __launch_bounds__(256)
+k_fbp_footprint(const float2 *cs, FbpDev p, FbpGridDev g, int4 *fp, int ntx, int nty, int ntz)
+{
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)g.nx * g.ny * ngz) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int kz0 = (int)(t / ((int64_t)g.nx * g.ny)) * kFbpZ;
+    const int64_t ntiles = (int64_t)ntx * nty * ntz;
+    if (t >= ntiles * p.n_angles) return;
+    const int a = (int)(t % p.n_angles);
+    const int64_t tile = t / p.n_angles;
+    const int tx = (int)(tile % ntx), ty = (int)((tile / ntx) % nty), tz = (int)(tile / ((int64_t)ntx * nty));
+    const int i0 = tx * kBpTile, i1 = min(i0 + kBpTile, g.nx) - 1;
+    const int j0 = ty * kBpTile, j1 = min(j0 + kBpTile, g.ny) - 1;
+    const int k0 = tz * kFbpZ, k1 = min(k0 + kFbpZ, g.nz) - 1;
+    const float z_lo = g.z0 + ((float)k0 + 0.5f) * g.dz, z_hi = g.z0 + ((float)k1 + 0.5f) * g.dz;
+    const float D = p.src_dist, rD = __builtin_amdgcn_rcpf(p.src_dist);
+    const float2 c = cs[a];
+    int umin = 1 << 30, umax = -(1 << 30), vmin = 1 << 30, vmax = -(1 << 30);
+    bool ok = true;
+    for (int corner = 0; corner < 4; ++corner) {
+        const int i = (corner & 1) ? i1 : i0, j = (corner & 2) ? j1 : j0;
+        const float xo = g.x0 + ((float)i + 0.5f) * g.dx;
+        const float yo = g.y0 + ((float)j + 0.5f) * g.dy;
+        int iu0, a0, a1;
+        if (!bp_indices(c, xo, yo, z_lo, z_hi, p, D, rD, iu0, a0, a1)) { ok = false; break; }
+        umin = min(umin, iu0); umax = max(umax, iu0);
+        vmin = min(vmin, a0); vmax = max(vmax, a1);
+    }
+    int4 r = make_int4(0, 0, 0, 0);
+    if (ok) {
+        // padded bins iu0 + 2 and iu0 + 3, rows iv0 + 2 and iv0 + 3, one more each side
+        const int ulo = max(umin + 1, 0), uhi = min(umax + 4, p.nu + 3);
+        const int vlo = max(vmin + 1, 0), vhi = min(vmax + 4, p.nv + 3);
+        r = make_int4(ulo, vlo, uhi - ulo + 1, vhi - vlo + 1);
+        if (r.z * r.w > kBpStage) r.z = 0;
+    }
+    fp[tile * p.n_angles + a] = r;
+}
+
+// Tiled backprojection: a block of kBpTile x kBpTile columns and one group of
+// kFbpZ slices stages, for each angle, the footprint of the tile on the
+// padded projection in LDS and samples it there; a footprint too large for
+// the stage is sampled from global memory.
+__global__ void __launch_bounds__(kBpTile * kBpTile)
+k_fbp_backproject_tiles(const float *q, const float2 *cs, const int4 *fp, FbpDev p, FbpGridDev g,
+                        float *image, uint8_t *mask, int ntx, int nty)
+{
+    __shared__ float stage[kBpStage];
+    const int tx = blockIdx.x % ntx, ty = (blockIdx.x / ntx) % nty, tz = blockIdx.x / (ntx * nty);
+    const int li = threadIdx.x % kBpTile, lj = threadIdx.x / kBpTile;
+    const int i = tx * kBpTile + li, j = ty * kBpTile + lj, kz0 = tz * kFbpZ;
+    const bool in = i < g.nx && j < g.ny;
     const int nzg = min(kFbpZ, g.nz - kz0);
     const float xo = g.x0 + ((float)i + 0.5f) * g.dx;
     const float yo = g.y0 + ((float)j + 0.5f) * g.dy;
@@ -423,35 +521,36 @@ k_fbp_backproject(const float *q, const float2 *cs, FbpDev p, FbpGridDev g, floa
         f[z] = 0.0f;
     }
     const float D = p.src_dist, rD = __builtin_amdgcn_rcpf(p.src_dist);
-    const int nu = p.nu, nv = p.nv, pu = nu + 4;
-    const int64_t pa = (int64_t)(nv + 4) * pu;
+    const int pu = p.nu + 4;
+    const int64_t pa = (int64_t)(p.nv + 4) * pu;
+    const int4 *fpt = fp + (int64_t)blockIdx.x * p.n_angles;
     for (int a = 0; a < p.n_angles; ++a) {
-        const float2 c = cs[a];
-        const float xl = c.x * xo - c.y * yo;
-        const float yl = c.y * xo + c.x * yo;
-        const float U = (D + xl) * rD;
-        if (!(U > 0.0f)) continue;   // voxel at or behind the source plane
-        const float iU = __builtin_amdgcn_rcpf(U);
-        const float w2 = iU * iU;
-        const float fu = (yl * iU - p.u0) * p.rdu - 0.5f;
-        const float fu0 = floorf(fu);
-        const float au = fu - fu0;
-        const int iu0 = min(max((int)fmaxf(fminf(fu0, 1.0e8f), -1.0e8f), -2), nu);
-        const float *qa = q + (int64_t)a * pa + (iu0 + 2);
-        const float fvs = iU * p.rdv;
-#pragma unroll
-        for (int z = 0; z < kFbpZ; ++z) {
-            const float fv = zo[z] * fvs - p.v0 * p.rdv - 0.5f;
-            const float fv0 = floorf(fv);
-            const float av = fv - fv0;
-            const int iv0 = min(max((int)fmaxf(fminf(fv0, 1.0e8f), -1.0e8f), -2), nv);
-            const float *q0 = qa + (int64_t)(iv0 + 2) * pu;
-            const float l0 = q0[0], r0 = q0[1], l1 = q0[pu], r1 = q0[pu + 1];
-            const float top = l0 + au * (r0 - l0);
-            const float bot = l1 + au * (r1 - l1);
-            f[z] += (top + av * (bot - top)) * w2;
+        const int4 r = fpt[a];   // the same in every lane
+        const float *qa = q + (int64_t)a * pa;
+        if (r.z > 0) {
+            __syncthreads();   // the previous angle's samples are taken
+            const int n = r.z * r.w;
+            const float rw = 1.0f / (float)r.z;
+            for (int e = threadIdx.x; e < n; e += blockDim.x) {
+                int row = (int)((float)e * rw);
+                if (row * r.z > e) --row;
+                if ((row + 1) * r.z <= e) ++row;
+                stage[e] = qa[(int64_t)(r.y + row) * pu + r.x + (e - row * r.z)];
+            }
+            __syncthreads();
+            if (in)
+                bp_term(cs[a], xo, yo, zo, f, p, D, rD, [&](int iv0, int iu0, int rr) {
+                    const float *s = stage + (iv0 + 2 + rr - r.y) * r.z + (iu0 + 2 - r.x);
+                    return make_float2(s[0], s[1]);
+                });
+        } else if (in) {
+            bp_term(cs[a], xo, yo, zo, f, p, D, rD, [&](int iv0, int iu0, int rr) {
+                const float *s = qa + (int64_t)(iv0 + 2 + rr) * pu + (iu0 + 2);
+                return make_float2(s[0], s[1]);
+            });
         }
     }
+    if (!in) return;
     for (int z = 0; z < nzg; ++z) {
         const float v = f[z] * p.half_dth;
         const int64_t vox = ((int64_t)(kz0 + z) * g.ny + j) * g.nx + i;
