@@ -351,8 +351,9 @@ k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *c
 }
 
 // One block per detector row: bin means, cosine pre-weight, then the
-// Shepp-Logan convolution along u (FP64 accumulation, rows taken as zero
-// outside the detector).
+// Shepp-Logan convolution along u (FP64 accumulation in the order j = 0 ..
+// nu - 1, rows taken as zero outside the detector).
+constexpr int kFilterOut = 4;
 __global__ void __launch_bounds__(256)
 k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p)
 {
@@ -380,11 +381,29 @@ k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDe
     // padded output: [n_angles][nv + 4][nu + 4], two zero bins on every side
     const int64_t k = r / p.nv;
     float *qr = q + (k * (p.nv + 4) + (iv + 2)) * (int64_t)(nu + 4) + 2;
-    for (int iu = threadIdx.x; iu < nu; iu += blockDim.x) {
-        double acc = 0.0;
-        const double *kr = ker + iu + nu - 1;
-        for (int j = 0; j < nu; ++j) acc += kr[-j] * row[j];
-        qr[iu] = (float)(du * acc);
+    // kFilterOut consecutive outputs per thread: output iu + c needs
+    // ker[iu + c + nu - 1 - j]; the window of kernel values slides down by one
+    // per j, so each j costs one kernel load and one (broadcast) row load
+    for (int iu = threadIdx.x * kFilterOut; iu < nu; iu += blockDim.x * kFilterOut) {
+        double acc[kFilterOut], win[kFilterOut];
+        const int top = iu + nu - 1;   // ker index of output iu at j = 0
+#pragma unroll
+        for (int c = 0; c < kFilterOut; ++c) {
+            acc[c] = 0.0;
+            win[c] = top + c < 2 * nu - 1 ? ker[top + c] : 0.0;
+        }
+#pragma unroll 8
+        for (int j = 0; j < nu; ++j) {
+            const double x = row[j];
+#pragma unroll
+            for (int c = 0; c < kFilterOut; ++c) acc[c] += win[c] * x;
+#pragma unroll
+            for (int c = kFilterOut - 1; c > 0; --c) win[c] = win[c - 1];
+            win[0] = top - j - 1 >= 0 ? ker[top - j - 1] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < kFilterOut; ++c)
+            if (iu + c < nu) qr[iu + c] = (float)(du * acc[c]);
     }
 }
 

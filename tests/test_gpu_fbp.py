@@ -68,3 +68,24 @@ def test_fbp_edge_histories():
     geo = spec.fbp_geometry(du=1.0, dv=2.5)
     img, mask, ref, rmask = _run(h, spec.grid, geo)
     _check(img, mask, ref, rmask, geo.threshold)
+
+
+@pytest.mark.parametrize("du,dv,path", [
+    (0.05, 0.5, "detector plane beyond the LDS: global binning; footprints beyond the stage"),
+    (0.25, 1.0, "one LDS plane per block"),
+])
+def test_fbp_fine_detectors_take_the_fallback_paths(du, dv, path):
+    """Fine detector sampling pushes the binning and the backprojection onto
+    their fallbacks (global sums, unstaged samples); they must give the same
+    image as the staged paths do, i.e. the oracle's within tolerance."""
+    g = gen.Grid((32, 32, 16), (1.0, 1.0, 2.5))
+    spec = gen.ScanSpec(g, 200_000, 36, gen.head_phantom(g), 0x5EED0110, sigma=1.0)
+    h = gen.generate(spec)
+    geo = spec.fbp_geometry(du=du, dv=dv)
+    plane_bytes = geo.nu * geo.nv * 12
+    if path.startswith("detector plane beyond"):
+        assert plane_bytes > 160 * 1024
+    else:
+        assert 80 * 1024 < plane_bytes <= 160 * 1024
+    img, mask, ref, rmask = _run(h, g, geo)
+    _check(img, mask, ref, rmask, geo.threshold)
