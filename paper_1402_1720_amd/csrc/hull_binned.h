@@ -46,7 +46,8 @@ struct BinWs {
     uint32_t *range_piece;  // [max_ranges] first final range of each coarse range
     unsigned long long *wprefix;  // [nsub + 1] work prefix of the sub-bins
     int32_t *ctl;           // kCtlWords
-    int32_t *rec;           // [B * kMaxSlicesPerLine][6] endpoints of each (history, slice) item
+    int32_t *rec;           // [B * kMaxSlicesPerLine][6] per item: the line's endpoints,
+                            // replaced by its slice-walk state (SliceState) for the tiles
     uint32_t *partial;      // [max_slots][tile_words]
     int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
     int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;
@@ -59,6 +60,7 @@ __global__ void k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGr
 __global__ void k_bin_scan_blocks(BinWs w);
 __global__ void k_bin_plan(BinWs w);
 __global__ void k_bin_scatter(int64_t nb, BinWs w);
+__global__ void k_item_setup(BinWs w, int nx, int ny);
 __global__ void k_walk_tiles(BinWs w, int nx, int ny);
 __global__ void k_reduce_tiles(BinWs w, int plane, int *N, int *M, hullmi_stats *st);
 __global__ void k_walk_overflow(BinWs w, int nx, int ny, int nz, int *N, int *M, hullmi_stats *st);

@@ -6,6 +6,7 @@
 //              work over the sorted item list
 //   scatter  : (history, slice) items in sub-bin order, each a copy of the
 //              history's 24-byte endpoint record
+//   setup    : each tile item's endpoints replaced by its slice-walk state
 //   walk     : persistent workgroups; each range is cut at slice boundaries
 //              into segments, each accumulated in a 16-bit LDS copy of its
 //              slice and written to its own partial slot
@@ -166,7 +167,11 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                         const int cls = low ? 0 : 1;
                         const int ns = k1 - k0 + 1;
                         meta = kMetaValid | (cls ? kMetaHigh : 0u) | ((uint32_t)ns << 12) | (uint32_t)k0;
-                        if (!tile_ok || ns > kMaxSlicesPerLine) {
+                        // the tile walk keeps its decision variable in 32 bits: that
+                        // needs |D| < 2^19 on x and y, else the global walk takes the line
+                        const int64_t adx = (int64_t)q[3] - q[0], ady = (int64_t)q[4] - q[1];
+                        const bool wide = max(adx < 0 ? -adx : adx, ady < 0 ? -ady : ady) >= (int64_t(1) << 19);
+                        if (!tile_ok || ns > kMaxSlicesPerLine || wide) {
                             meta |= kMetaOverflow;
                             atomicAdd(&lh[w.nsub - 2 + cls], 1u);
                         } else {
@@ -351,12 +356,12 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
             x.a = src[0]; x.b = src[1]; x.c = src[2];
         }
     };
-    Next nx;
-    fetch(0, nx);
+    Next nxt;
+    fetch(0, nxt);
     for (int r = 0; r < kHistPerThread; ++r) {
         if (base + (int64_t)r * kBinThreads >= nb) break;
-        const Next cu = nx;
-        fetch(r + 1, nx);
+        const Next cu = nxt;
+        fetch(r + 1, nxt);
         const uint32_t m = cu.m;
         if (!(m & kMetaValid)) continue;
         const int cls = (m & kMetaHigh) ? 1 : 0;
@@ -376,29 +381,35 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
     }
 }
 
-// 16-bit counters packed in pairs into 32-bit LDS words; the walk hands over
-// the byte offset 2 * voxel of the counter.
-struct LdsAcc16 {
-    uint32_t *t;
-    __device__ __forceinline__ void operator()(int boff) const
-    {
-        const uint32_t b = (uint32_t)boff;
-        atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(t) + (b & ~3u)),
-                  1u + 65535u * __builtin_amdgcn_ubfe(b, 1u, 1u));
+// Replaces the endpoints of every tile item by its slice-walk state (one item
+// per lane, grid-stride over the items counted on the device), so that the
+// walk's lanes only run the loop.
+__global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
+{
+    const int n = w.ctl[kCtlItems];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const int t = count_le(w.tile_start, 0, w.ntiles, (uint32_t)p) - 1;   // slice tile of p
+        int2 *r = reinterpret_cast<int2 *>(w.rec + 6 * (size_t)p);
+        const int2 a = r[0], b = r[1], c = r[2];
+        SliceState st;
+        slice_state(a.x, a.y, b.x, b.y, c.x, c.y, nx, ny, t % w.nz, st);
+        r[0] = make_int2(st.d, st.first);
+        r[1] = make_int2(st.last, st.incx);
+        r[2] = make_int2(st.incy, st.steps);
     }
-};
+}
 
 // Persistent workgroups over the ranges; a range is cut at slice boundaries
 // into segments, each accumulated in the LDS copy of its slice and written to
-// its partial slot. The next item's endpoints are loaded while the current
-// line is walked.
+// its partial slot. Items carry their slice-walk state (k_item_setup), so a
+// lane only runs the loop; the next item's state is loaded while the current
+// one is walked.
 __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, int ny)
 {
-    extern __shared__ uint32_t lds[];   // tile (tile_words), then 3 control words
+    extern __shared__ uint32_t lds[];   // tile (tile_words), then 2 control words
     uint32_t *tile = lds;
     uint32_t *seg = lds + w.tile_words;
     const int nranges = w.ctl[kCtlRanges];
-    LdsAcc16 acc{tile};
     // LDS byte address of the tile (the low 32 bits of a local pointer)
     const uint32_t tile_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)tile;
     for (int r = blockIdx.x; r < nranges; r += gridDim.x) {
@@ -407,15 +418,12 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
         while (x < b) {
             if (threadIdx.x == 0) {
                 const int t = count_le(w.tile_start, 0, w.ntiles, x) - 1;   // slice holding x
-                seg[0] = (uint32_t)t;
-                seg[1] = min(b, w.tile_start[t + 1]);
-                seg[2] = (uint32_t)slot_of(w, nranges, x);
+                seg[0] = min(b, w.tile_start[t + 1]);
+                seg[1] = (uint32_t)slot_of(w, nranges, x);
             }
             for (int i = threadIdx.x; i < w.tile_words; i += blockDim.x) tile[i] = 0;
             __syncthreads();
-            const int t = (int)seg[0];
-            const uint32_t y = seg[1], slot = seg[2];
-            const int k = t % w.nz;
+            const uint32_t y = seg[0], slot = seg[1];
             // the next item's record (contiguous across the workgroup) is in
             // flight while the current line is walked
             const uint32_t S = blockDim.x;
@@ -431,9 +439,16 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
                     const int2 *r = reinterpret_cast<const int2 *>(w.rec + 6 * (size_t)(it + S));
                     c0 = r[0]; c1 = r[1]; c2 = r[2];
                 }
-                walk_slice_tile16(a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, nx, ny, k, tile_base, acc);
+                if (a0.y >= 0)   // a slice the line meets
+                    walk_slice_lds16(a0.x, (int32_t)tile_base + a0.y, (int32_t)tile_base + a1.x,
+                                     a1.y, a2.x, (int32_t)(int16_t)(a2.y & 0xffff), a2.y >> 16,
+                                     nx + ny);
                 it += S;
             }
+            // the loop's LDS adds are issued from inline assembly, which the
+            // compiler's wait counting does not see: wait for them here, or a
+            // barrier could let another wave flush a word before they land
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             __syncthreads();
             uint32_t *dst = w.partial + (int64_t)slot * w.tile_words;
             for (int i = threadIdx.x; i < w.tile_words; i += blockDim.x) dst[i] = tile[i];

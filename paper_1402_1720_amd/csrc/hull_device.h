@@ -192,44 +192,21 @@ __device__ __forceinline__ int walk_line(int qix, int qiy, int qiz, int qox, int
 
 namespace hullmi {
 
-// The part of A_i inside z-slice k, enumerated exactly. Inside one slice the
-// z index is constant, so once the first and the last voxel are known (the
-// last is the first voxel of the reversed line, since A_i does not depend on
-// the direction) the walk needs only the x/y decision variable: an axis steps
-// when it comes strictly first, both step when they tie (the line passes
-// through a voxel corner with both indices moving the same way; mixed
-// directions never tie, the sigma term breaks it). acc(S * (i + nx * j)) is
-// called once per voxel. The loop runs at most nx + ny times whatever happens.
-template <int S, typename T, class Acc>
-__device__ __forceinline__ void walk_slice_run(const WalkInit &a, int last, int nx, int ny, Acc &acc)
-{
-    T d = (T)a.dxy;
-    const T incx = (T)(2048 * a.Ay), incy = (T)(-2048 * a.Ax), incxy = incx + incy;
-    const int ox = S * a.sx, oy = S * a.sy * nx, oxy = ox + oy;
-    int off = S * (a.cx + nx * a.cy);
-    // the iteration count is the same in every lane (a scalar register): the
-    // loop ends when no lane is live or after nx + ny rounds
-    const int maxit = nx + ny;
-    bool live = true;
-    for (int it = 0; it < maxit; ++it) {
-        if (live) {
-            acc(off);
-            live = off != last;
-            const bool bx = d < 0, tie = d == 0;
-            d += bx ? incx : (tie ? incxy : incy);
-            off += bx ? ox : (tie ? oxy : oy);
-        }
-        if (!__any(live)) break;
-    }
-}
-
-// The same loop for the 16-bit LDS tile written directly in gfx950 assembly
-// (the compiler keeps the loop guard and the any-lane test in vector
-// registers; here they are scalar): per step 12 VALU instructions and one
-// ds_add_u32. Lanes leave the exec mask when they have visited `last`; the
-// loop also ends after maxit rounds. Only LDS is touched: `off` and `last` are
-// LDS byte addresses of 16-bit counters (tile base + 2 * voxel, the base a
-// multiple of 4), so the word is off & ~3 and the half is bit 1 of off.
+// The part of A_i inside one z-slice. The z index is constant there, so once
+// the first and the last voxel are known (the last is the first voxel of the
+// reversed line, since A_i does not depend on the direction) the walk needs
+// only the x/y decision variable d: x steps when d < 0, y when d > 0, both
+// when d = 0 (the line passes through a voxel corner with both indices moving
+// the same way; mixed directions never tie, the sigma term breaks it), and
+// every step changes d by incx, incy or both.
+//
+// The loop is written directly in gfx950 assembly (the compiler keeps the loop
+// guard and the any-lane test in vector registers; here they are scalar): per
+// step 12 VALU instructions and one ds_add_u32 into the 16-bit LDS tile. Lanes
+// leave the exec mask when they have visited `last`; the loop also ends after
+// maxit rounds. Only LDS is touched: `off` and `last` are LDS byte addresses
+// of 16-bit counters (tile base + 2 * voxel, the base a multiple of 4), so the
+// word is off & ~3 and the half is bit 1 of off.
 __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t last,
                                                  int32_t incx, int32_t incy, int32_t ox,
                                                  int32_t oy, int32_t maxit)
@@ -270,39 +247,35 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
         : "vcc", "scc", "memory");
 }
 
-// A_i inside slice k accumulated into a 16-bit LDS tile at LDS byte address
-// `base` (see walk_slice for the set-up; this variant uses walk_slice_lds16
-// for the common case of |D| < 2^19 and the C++ loop otherwise).
-template <class Acc>
-__device__ __forceinline__ void walk_slice_tile16(int qix, int qiy, int qiz, int qox, int qoy,
-                                                  int qoz, int nx, int ny, int k, uint32_t base,
-                                                  Acc &acc)
-{
-    const int zs = k * kQ;
-    WalkInit a, b;
-    if (!walk_init(qix, qiy, qiz - zs, qox, qoy, qoz - zs, nx, ny, 1, a)) return;
-    if (!walk_init(qox, qoy, qoz - zs, qix, qiy, qiz - zs, nx, ny, 1, b)) return;
-    const int last = 2 * (b.cx + nx * b.cy);
-    if (max(a.Ax, a.Ay) < (int64_t(1) << 19)) {
-        walk_slice_lds16((int32_t)a.dxy, (int32_t)base + 2 * (a.cx + nx * a.cy),
-                         (int32_t)base + last, (int32_t)(2048 * a.Ay), (int32_t)(-2048 * a.Ax),
-                         2 * a.sx, 2 * a.sy * nx, nx + ny);
-    } else {
-        walk_slice_run<2, int64_t>(a, last, nx, ny, acc);
-    }
-}
+// Walk state of A_i inside z-slice k for walk_slice_lds16, set up once per
+// (line, slice) from two walk_init calls restricted to the slice (forward for
+// the first voxel and d, reversed for the last voxel): the decision
+// variable, the byte offsets 2 * voxel of the first and the last
+// voxel, the changes of d per x and per y step, and the byte steps per x step
+// (low 16 bits of `steps`, signed) and per y step (high 16 bits, signed).
+// first = last = -1 when the line does not meet the slice inside the grid.
+// Exact when |D| < 2^19 on x and y (the int32 condition of the loop).
+struct SliceState {
+    int32_t d, first, last, incx, incy, steps;
+};
 
-template <int S, class Acc>
-__device__ __forceinline__ void walk_slice(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
-                                           int nx, int ny, int k, Acc &acc)
+__device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                            int nx, int ny, int k, SliceState &s)
 {
     const int zs = k * kQ;
     WalkInit a, b;
-    if (!walk_init(qix, qiy, qiz - zs, qox, qoy, qoz - zs, nx, ny, 1, a)) return;
-    if (!walk_init(qox, qoy, qoz - zs, qix, qiy, qiz - zs, nx, ny, 1, b)) return;
-    const int last = S * (b.cx + nx * b.cy);
-    if (max(a.Ax, a.Ay) < (int64_t(1) << 19)) walk_slice_run<S, int32_t>(a, last, nx, ny, acc);
-    else walk_slice_run<S, int64_t>(a, last, nx, ny, acc);
+    if (!walk_init(qix, qiy, qiz - zs, qox, qoy, qoz - zs, nx, ny, 1, a) ||
+        !walk_init(qox, qoy, qoz - zs, qix, qiy, qiz - zs, nx, ny, 1, b)) {
+        s.d = 0; s.first = -1; s.last = -1; s.incx = 0; s.incy = 0; s.steps = 0;
+        return;
+    }
+    s.d = (int32_t)a.dxy;
+    s.first = 2 * (a.cx + nx * a.cy);
+    s.last = 2 * (b.cx + nx * b.cy);
+    s.incx = (int32_t)(2048 * a.Ay);
+    s.incy = (int32_t)(-2048 * a.Ax);
+    const int32_t ox = 2 * a.sx, oy = 2 * a.sy * nx;
+    s.steps = (int32_t)(((uint32_t)oy << 16) | ((uint32_t)ox & 0xffffu));
 }
 
 // z index of the first voxel of A_i (the cz of walk_init), or -1 when the line
