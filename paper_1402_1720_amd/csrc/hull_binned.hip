@@ -1,6 +1,7 @@
 // Slice-binned counting kernels. A batch of histories goes through:
-//   classify : class, geometry, exact z-slice range of A_i, a length class per
-//              slice, per-block counts of the sub-bins (class, slice, length)
+//   classify : class, geometry, whether A_i is empty (exact), a z-slice range
+//              that covers A_i, a length class per slice, per-block counts of
+//              the sub-bins (class, slice, length)
 //   scan     : per sub-bin offsets of every block
 //   plan     : sub-bin starts, slice (tile) starts, ranges of equal estimated
 //              work over the sorted item list
@@ -161,9 +162,12 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                 } else {
                     if (low) ++nl; else ++nh;
                     int k0, k1;
-                    if (!line_z_range(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz, k0, k1)) {
+                    // exact test for an empty A_i, then a slice range that covers A_i
+                    // (a slice the line does not meet gives an empty item)
+                    if (!line_meets_grid(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz)) {
                         ++nmi;
                     } else {
+                        line_z_cover(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz, k0, k1);
                         const int cls = low ? 0 : 1;
                         const int ns = k1 - k0 + 1;
                         meta = kMetaValid | (cls ? kMetaHigh : 0u) | ((uint32_t)ns << 12) | (uint32_t)k0;

@@ -278,13 +278,13 @@ __device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, 
     s.steps = (int32_t)(((uint32_t)oy << 16) | ((uint32_t)ox & 0xffffu));
 }
 
-// z index of the first voxel of A_i (the cz of walk_init), or -1 when the line
-// misses the grid (exactly when walk_init returns false). The x and y indices
-// at the entry key are only range-checked, which needs no division: for
-// den > 0, floor(num / den) lies in [0, n) iff 0 <= num < n den, and
-// ceil(num / den) - 1 lies in [0, n) iff 0 < num <= n den.
-__device__ __forceinline__ int entry_z(int qix, int qiy, int qiz, int qox, int qoy, int qoz, int nx,
-                                       int ny, int nz)
+// Whether A_i is not empty, exactly when walk_init returns true: the entry key
+// as walk_init picks it, then every axis only range-checked, which needs no
+// division (for den > 0, floor(num / den) lies in [0, n) iff
+// 0 <= num < n den, and ceil(num / den) - 1 lies in [0, n) iff
+// 0 < num <= n den).
+__device__ __forceinline__ bool line_meets_grid(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                                int nx, int ny, int nz)
 {
     const int64_t P[3] = {qix, qiy, qiz};
     const int64_t D[3] = {(int64_t)qox - qix, (int64_t)qoy - qiy, (int64_t)qoz - qiz};
@@ -296,10 +296,9 @@ __device__ __forceinline__ int entry_z(int qix, int qiy, int qiz, int qox, int q
     for (int b = 0; b < 3; ++b) {
         const int64_t L = (int64_t)kQ * n[b];
         if (D[b] == 0) {
-            if (P[b] < 0 || P[b] >= L) return -1;   // a fixed axis outside the grid
+            if (P[b] < 0 || P[b] >= L) return false;
             continue;
         }
-        // entry key of axis b: t = en / A, sigma = (D < 0); the latest one wins
         const int64_t A = D[b] < 0 ? -D[b] : D[b];
         const int64_t en = D[b] > 0 ? -P[b] : P[b] - L;
         const int g = D[b] < 0;
@@ -310,38 +309,48 @@ __device__ __forceinline__ int entry_z(int qix, int qiy, int qiz, int qox, int q
         wa = b; ew = en; aw = A; gw = g;
     }
     const int64_t den = (int64_t)kQ * aw;
-    int cz = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        int64_t c;
-        if (b == wa) {
-            c = D[b] > 0 ? 0 : n[b] - 1;
-        } else if (D[b] == 0) {
-            c = P[b] >> 10;
-        } else {
-            const int64_t num = P[b] * aw + D[b] * ew;
-            const bool up = gw && D[b] < 0;   // the ceiling form of walk_init
-            if (up ? (num <= 0 || num > (int64_t)n[b] * den) : (num < 0 || num >= (int64_t)n[b] * den))
-                return -1;
-            c = b == 2 ? (up ? -floor_div_small(-num, den) - 1 : floor_div_small(num, den)) : 0;
-        }
-        if (b == 2) cz = (int)c;
+        if (b == wa || D[b] == 0) continue;
+        const int64_t num = P[b] * aw + D[b] * ew;
+        const bool up = gw && D[b] < 0;
+        if (up ? (num <= 0 || num > (int64_t)n[b] * den) : (num < 0 || num >= (int64_t)n[b] * den))
+            return false;
     }
-    return cz;
+    return true;
 }
 
-// z-index range of A_i over the whole grid: the first voxel of the line and of
-// the reversed line. Returns false when the line misses the grid.
-__device__ __forceinline__ bool line_z_range(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+// A range of z-slices that holds every slice A_i meets (for a line that meets
+// the grid): the z extent of the line's part inside the grid box in FP32,
+// widened by far more than its rounding error. Slices it adds that the line
+// does not meet are found empty by the exact slice set-up.
+__device__ __forceinline__ void line_z_cover(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
                                              int nx, int ny, int nz, int &k0, int &k1)
 {
-    const int a = entry_z(qix, qiy, qiz, qox, qoy, qoz, nx, ny, nz);
-    if (a < 0) return false;
-    const int b = entry_z(qox, qoy, qoz, qix, qiy, qiz, nx, ny, nz);
-    if (b < 0) return false;
-    k0 = min(a, b);
-    k1 = max(a, b);
-    return true;
+    const float s = 1.0f / (float)kQ;
+    const float p[3] = {qix * s, qiy * s, qiz * s};
+    const float d[3] = {(float)((int64_t)qox - qix) * s, (float)((int64_t)qoy - qiy) * s,
+                        (float)((int64_t)qoz - qiz) * s};
+    const float n[3] = {(float)nx, (float)ny, (float)nz};
+    float tlo = -3.0e38f, thi = 3.0e38f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0f) {
+            const float t0 = (0.0f - p[a]) / d[a], t1 = (n[a] - p[a]) / d[a];
+            tlo = fmaxf(tlo, fminf(t0, t1));
+            thi = fminf(thi, fmaxf(t0, t1));
+        }
+    }
+    float za = p[2], zb = p[2];
+    if (d[2] != 0.0f) {
+        za = p[2] + tlo * d[2];
+        zb = p[2] + thi * d[2];
+    }
+    const float lo = fminf(za, zb), hi = fmaxf(za, zb);
+    const float m = (fabsf(p[2]) + fabsf(lo) + fabsf(hi) + n[2]) * (1.0f / 65536.0f) + 1.0f / 1024.0f;
+    k0 = (int)fmaxf(floorf(lo - m), 0.0f);
+    k1 = (int)fminf(floorf(hi + m), n[2] - 1.0f);
+    if (k1 < k0) k1 = k0;   // cannot happen for a line that meets the grid
 }
 
 }  // namespace hullmi
