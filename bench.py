@@ -324,7 +324,7 @@ def main():
     reps = max(3, args.steps)
     # the counting pass alone: with ACCUMULATE and no masks hull_all launches
     # only the slice-binned counting kernels (classify, scan, plan, scatter,
-    # tile walk, reduce, overflow walk) on `stream`
+    # item set-up, tile walk, reduce, overflow walk) on `stream`
     t_walk = timed(lambda: H.hull_all(hist, grid, params, N, M, flags=H.HULL_ACCUMULATE,
                                       ws=ws_all, stream=stream), reps)
     t_all = timed(lambda: H.hull_all(hist, grid, params, N, M, sc, msc, sm, ws=ws_all,
@@ -371,7 +371,8 @@ def main():
                  "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
         "roofline": {"bound": "alu",
                      "kernel": "counting pass: k_bin_classify + k_bin_scan_blocks + k_bin_plan + "
-                               "k_bin_scatter + k_walk_tiles + k_reduce_tiles + k_walk_overflow",
+                               "k_bin_scatter + k_item_setup + k_walk_tiles + k_reduce_tiles + "
+                               "k_walk_overflow",
                      "per_unit": "6 int32 lane-ops per voxel visit", "units": visits,
                      "achieved": achieved_tops,
                      "peak": PEAK_INT_TOPS, "unit": "TOP/s", "frac": achieved_tops / PEAK_INT_TOPS,
