@@ -79,6 +79,23 @@ class OrFbpParams(ctypes.Structure):
                 ("filter", ctypes.c_int32), ("threshold", ctypes.c_float)]
 
 
+class OrBscParams(ctypes.Structure):
+    """Binned SC: cutoff E_L (mm), data cut at k standard deviations (0 = off),
+    averaging window W (odd) and the keep threshold num/den."""
+    _fields_ = [("wepl_low", ctypes.c_float), ("cut_sigmas", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("thr_num", ctypes.c_int32),
+                ("thr_den", ctypes.c_int32)]
+
+
+class OrBscStats(ctypes.Structure):
+    _fields_ = [("n_binned", ctypes.c_int64), ("n_cut", ctypes.c_int64),
+                ("n_bins_used", ctypes.c_int64), ("n_bins_carved", ctypes.c_int64),
+                ("n_lines_skipped", ctypes.c_int64), ("n_visits", ctypes.c_int64)]
+
+    def as_dict(self) -> Dict[str, int]:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _handle = None
 
 
@@ -112,6 +129,10 @@ def _lib():
                                 ctypes.c_int, P, P, P], ctypes.c_int),
             "oracle_hull_all": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "oracle_hull_fbp": ([P, P, P, P, P], ctypes.c_int),
+            "or_bsc_line": ([P, P, i32, i32, i32, P, P], ctypes.c_int),
+            "or_bsc_blur": ([P, P, i32, i32, i32, P], None),
+            "or_bsc": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
+            "oracle_hull_sc_binned": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -283,6 +304,46 @@ def fbp(hist, grid: OrGrid, p: OrFbpParams):
     return img, mask, proj, int(used)
 
 
+def bsc_params(wepl_low: float = 1.0, cut_sigmas: int = 3, window: int = 5, thr_num: int = 2,
+               thr_den: int = 5) -> OrBscParams:
+    """Binned SC parameters; the defaults are the paper's (Sections 2.2, 3.2):
+    E_L = 1.0 mm, 3-sigma cuts, 5 x 5 averaging, threshold 0.4."""
+    return OrBscParams(wepl_low, cut_sigmas, window, thr_num, thr_den)
+
+
+def bsc_line(p: OrFbpParams, grid: OrGrid, k: int, iu: int, iv: int):
+    """(status, qin, qout): the quantised carve line of bin (k, iu, iv)."""
+    qin = np.zeros(3, np.int32)
+    qout = np.zeros(3, np.int32)
+    st = _lib().or_bsc_line(ctypes.byref(p), ctypes.byref(grid), int(k), int(iu), int(iv),
+                            _ptr(qin), _ptr(qout))
+    return int(st), qin, qout
+
+
+def bsc_blur(carved: np.ndarray, grid: OrGrid, window: int = 5, thr_num: int = 2,
+             thr_den: int = 5) -> np.ndarray:
+    c = np.ascontiguousarray(carved, dtype=np.uint8).reshape(-1)
+    mask = np.empty(c.size, np.uint8)
+    _lib().or_bsc_blur(_ptr(c), ctypes.byref(grid), int(window), int(thr_num), int(thr_den),
+                       _ptr(mask))
+    return mask
+
+
+def sc_binned(hist, grid: OrGrid, p: OrFbpParams, bp: Optional[OrBscParams] = None):
+    """Binned SC: dict with kept_n, kept_sum (per bin, 1/1024 mm), carved,
+    mask and stats."""
+    bp = bp if bp is not None else bsc_params()
+    hv = _HistView(hist)
+    V = _vox(grid)
+    nb = int(p.n_angles) * int(p.nv) * int(p.nu)
+    kn, ks = np.empty(nb, np.uint32), np.empty(nb, np.int64)
+    carved, mask, st = np.empty(V, np.uint8), np.empty(V, np.uint8), OrBscStats()
+    if _lib().or_bsc(ctypes.byref(hv.c), ctypes.byref(grid), ctypes.byref(p), ctypes.byref(bp),
+                     _ptr(kn), _ptr(ks), _ptr(carved), _ptr(mask), ctypes.byref(st)) != 0:
+        raise ValueError("binned SC rejected its arguments")
+    return dict(kept_n=kn, kept_sum=ks, carved=carved, mask=mask, stats=st.as_dict())
+
+
 # ---------------------------------------------------------------------------
 # whole-call mirrors of the GPU library's per-scan calls (host arrays)
 
@@ -347,3 +408,17 @@ def hull_fbp(hist, grid: OrGrid, p: OrFbpParams):
                               _ptr(mask)) != 0:
         raise ValueError("oracle_hull_fbp rejected its arguments")
     return img, mask
+
+
+def hull_sc_binned(hist, grid: OrGrid, p: OrFbpParams, bp: OrBscParams):
+    """(kept_n, kept_sum, carved, mask, stats) through the mirror call."""
+    hv = _HistView(hist)
+    V = _vox(grid)
+    nb = int(p.n_angles) * int(p.nv) * int(p.nu)
+    kn, ks = np.empty(nb, np.uint32), np.empty(nb, np.int64)
+    carved, mask, st = np.empty(V, np.uint8), np.empty(V, np.uint8), OrBscStats()
+    if _lib().oracle_hull_sc_binned(ctypes.byref(hv.c), ctypes.byref(grid), ctypes.byref(p),
+                                    ctypes.byref(bp), _ptr(kn), _ptr(ks), _ptr(carved), _ptr(mask),
+                                    ctypes.byref(st)) != 0:
+        raise ValueError("oracle_hull_sc_binned rejected its arguments")
+    return kn, ks, carved, mask, st.as_dict()

@@ -29,6 +29,10 @@
  *   6. FDK cone-beam FBP hull (Section 3.1): bin, cosine weight, Shepp-Logan
  *      filter, weighted backprojection, threshold RSP >= 0.6. FP64 throughout,
  *      except that the bin a history falls in is decided in FP32.
+ *   7. Binned SC (Section 3.2 as the paper ran it, with Section 2.2's data
+ *      cuts): per-bin WEPL cuts at k standard deviations, one carve line per
+ *      bin whose kept mean WEPL is below E_L, then a W x W averaging filter
+ *      and a threshold. Integer statistics in 1/1024 mm fixed point.
  *
  * Every function here is pinned by the test suite to something other than
  * itself (brute force with exact fractions, hand-derived cases, closed forms,
@@ -415,36 +419,43 @@ int or_sm(const int32_t *M, const or_grid *g, int32_t num, int32_t den, int mode
  * everything else is FP64. Histories with a non-finite field, |WEPL| >= 2^16 mm
  * (far beyond any proton range) or x_out == x_in are not binned.
  * proj: [n_angles][nv][nu]. Returns the number of histories binned. */
+/* The bin of history i: -1 when it is not binned, else (k nv + iv) nu + iu. */
+static int64_t or_bin_of(const or_hist *h, int64_t i, const or_fbp_params *p)
+{
+    const float rdu = 1.0f / p->du_mm, rdv = 1.0f / p->dv_mm, rda = 1.0f / p->dangle_deg;
+    const float xi = h->x_in[i], yi = h->y_in[i], zi = h->z_in[i];
+    const float xo = h->x_out[i], yo = h->y_out[i], zo = h->z_out[i];
+    const float a = h->angle_deg[i], w = h->wepl[i];
+    if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
+          isfinite(zo) && isfinite(a) && isfinite(w)))
+        return -1;
+    if (!(fabsf(w) < 65536.0f)) return -1;
+    const float ddx = xo - xi;
+    if (ddx == 0.0f) return -1;
+    const float r = (0.0f - xi) / ddx;
+    const float u = yi + r * (yo - yi);
+    const float v = zi + r * (zo - zi);
+    const float fa = (a - p->angle0_deg) * rda;
+    const float fu = (u - p->u0_mm) * rdu;
+    const float fv = (v - p->v0_mm) * rdv;
+    if (!(fabsf(fa) < 1.0e9f)) return -1;
+    if (!(fu >= 0.0f && fu < (float)p->nu && fv >= 0.0f && fv < (float)p->nv)) return -1;
+    long k = lrintf(fa) % p->n_angles;
+    if (k < 0) k += p->n_angles;
+    const int64_t iu = (int64_t)floorf(fu), iv = (int64_t)floorf(fv);
+    return ((int64_t)k * p->nv + iv) * p->nu + iu;
+}
+
 int64_t or_fbp_bin(const or_hist *h, const or_fbp_params *p, double *proj)
 {
     const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
     double *cnt = (double *)calloc((size_t)nb, sizeof(double));
     for (int64_t b = 0; b < nb; ++b) proj[b] = 0.0;
-    const float rdu = 1.0f / p->du_mm, rdv = 1.0f / p->dv_mm, rda = 1.0f / p->dangle_deg;
     int64_t used = 0;
     for (int64_t i = 0; i < h->n; ++i) {
-        const float xi = h->x_in[i], yi = h->y_in[i], zi = h->z_in[i];
-        const float xo = h->x_out[i], yo = h->y_out[i], zo = h->z_out[i];
-        const float a = h->angle_deg[i], w = h->wepl[i];
-        if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
-              isfinite(zo) && isfinite(a) && isfinite(w)))
-            continue;
-        if (!(fabsf(w) < 65536.0f)) continue;
-        const float ddx = xo - xi;
-        if (ddx == 0.0f) continue;
-        const float r = (0.0f - xi) / ddx;
-        const float u = yi + r * (yo - yi);
-        const float v = zi + r * (zo - zi);
-        const float fa = (a - p->angle0_deg) * rda;
-        const float fu = (u - p->u0_mm) * rdu;
-        const float fv = (v - p->v0_mm) * rdv;
-        if (!(fabsf(fa) < 1.0e9f)) continue;
-        if (!(fu >= 0.0f && fu < (float)p->nu && fv >= 0.0f && fv < (float)p->nv)) continue;
-        long k = lrintf(fa) % p->n_angles;
-        if (k < 0) k += p->n_angles;
-        const int64_t iu = (int64_t)floorf(fu), iv = (int64_t)floorf(fv);
-        const int64_t b = ((int64_t)k * p->nv + iv) * p->nu + iu;
-        proj[b] += (double)w;
+        const int64_t b = or_bin_of(h, i, p);
+        if (b < 0) continue;
+        proj[b] += (double)h->wepl[i];
         cnt[b] += 1.0;
         ++used;
     }
@@ -550,6 +561,157 @@ int64_t or_fbp(const or_hist *h, const or_grid *g, const or_fbp_params *p, doubl
     return used;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Binned SC with data cuts and a blur: the form in which the paper ran SC   */
+/* (Section 3.2, after Algorithm 1; the data cuts of Section 2.2).           */
+/*   1. Bin histories by (gantry angle, u, v) where their line crosses x = 0, */
+/*      the bins of the FDK hull (decided in FP32 by or_bin_of).              */
+/*   2. Per bin: mean and standard deviation of WEPL; drop each history      */
+/*      whose WEPL lies more than k standard deviations from its bin's mean  */
+/*      (the record has no angles, so only WEPL is cut).                      */
+/*   3. A bin whose remaining histories have mean WEPL below E_L is taken as  */
+/*      a miss: the voxels of its line are carved. The bin's line runs from  */
+/*      the source through the bin centre on the detector plane, and its     */
+/*      voxels are A of that line (steps 2-3 above, the same rounding).      */
+/*   4. A W x W in-plane averaging filter over the uncarved image (voxels    */
+/*      outside the grid count as carved), then keep a voxel iff its window  */
+/*      mean exceeds num/den.                                                */
+/* Reading for exactness: WEPL enters the statistics in fixed point,         */
+/* w_q = rint(WEPL * 1024) (1/1024 mm), as does the cutoff e_q; sums are     */
+/* exact integers, sigma is the population deviation, and "more than k sigma"*/
+/* is (n w_q - S1)^2 > k^2 (n S2 - S1^2) with S1 = sum w_q, S2 = sum w_q^2.  */
+/* A bin is carved iff it keeps at least one history and S1' < e_q n'.       */
+
+typedef struct {
+    float wepl_low;            /* E_L, mm: a bin with kept mean WEPL below it is carved */
+    int32_t cut_sigmas;        /* k; 0 turns the data cuts off */
+    int32_t window;            /* W, odd */
+    int32_t thr_num, thr_den;  /* keep iff window mean > num / den */
+} or_bsc_params;
+
+typedef struct {
+    int64_t n_binned, n_cut, n_bins_used, n_bins_carved, n_lines_skipped, n_visits;
+} or_bsc_stats;
+
+/* The carve line of bin (k, iu, iv) as quantised object-frame endpoints:
+ * source (-D, 0, 0) and bin centre (0, u_c, v_c) in the lab frame at gantry
+ * angle theta_k = angle0 + k dangle, all in FP32. Returns OR_OK or a skip
+ * reason (as for a history). */
+int or_bsc_line(const or_fbp_params *p, const or_grid *g, int32_t k, int32_t iu, int32_t iv,
+                int32_t qin[3], int32_t qout[3])
+{
+    const float uc = p->u0_mm + ((float)iu + 0.5f) * p->du_mm;
+    const float vc = p->v0_mm + ((float)iv + 0.5f) * p->dv_mm;
+    const float th = p->angle0_deg + (float)k * p->dangle_deg;
+    if (!(isfinite(uc) && isfinite(vc) && isfinite(th))) return OR_SKIP_NONFINITE;
+    float c, s;
+    or_trig(th, &c, &s);
+    int st = or_point(c, s, -p->src_dist_mm, 0.0f, 0.0f, g, qin);
+    if (st == OR_OK) st = or_point(c, s, 0.0f, uc, vc, g, qout);
+    if (st != OR_OK) return st;
+    if (qin[0] == qout[0] && qin[1] == qout[1] && qin[2] == qout[2]) return OR_SKIP_DEGENERATE;
+    return OR_OK;
+}
+
+/* Step 4: mask[v] = [den * (number of uncarved voxels of the W x W window
+ * around v in its slice) > num * W^2]. */
+void or_bsc_blur(const uint8_t *carved, const or_grid *g, int32_t W, int32_t num, int32_t den,
+                 uint8_t *mask)
+{
+    const int64_t nx = g->nx, ny = g->ny, nz = g->nz, r = W / 2;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t sum = 0;
+                for (int64_t b = j - r; b <= j + r; ++b)
+                    for (int64_t a = i - r; a <= i + r; ++a)
+                        if (a >= 0 && a < nx && b >= 0 && b < ny)
+                            sum += carved[(k * ny + b) * nx + a] ? 0 : 1;
+                mask[(k * ny + j) * nx + i] =
+                    (uint8_t)((int64_t)den * sum > (int64_t)num * W * W);
+            }
+}
+
+/* Steps 1-4. kept_n, kept_sum (both [n_angles][nv][nu], sums in 1/1024 mm),
+ * carved and mask may each be NULL. Returns 0, or 1 for a bad argument. */
+int or_bsc(const or_hist *h, const or_grid *g, const or_fbp_params *p, const or_bsc_params *bp,
+           uint32_t *kept_n, int64_t *kept_sum, uint8_t *carved, uint8_t *mask, or_bsc_stats *st)
+{
+    if (!(isfinite(bp->wepl_low) && fabsf(bp->wepl_low) < 65536.0f)) return 1;
+    if (bp->cut_sigmas < 0 || bp->cut_sigmas > 64) return 1;
+    if (bp->window < 1 || bp->window % 2 == 0 || bp->thr_den <= 0) return 1;
+    const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    const __int128 k2 = (__int128)bp->cut_sigmas * bp->cut_sigmas;
+    const int64_t e_q = llrint((double)bp->wepl_low * 1024.0);
+    int64_t *bin = (int64_t *)malloc((size_t)(h->n > 0 ? h->n : 1) * sizeof(int64_t));
+    int64_t *wq = (int64_t *)malloc((size_t)(h->n > 0 ? h->n : 1) * sizeof(int64_t));
+    int64_t *n = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    int64_t *s1 = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    __int128 *s2 = (__int128 *)calloc((size_t)nb, sizeof(__int128));
+    int64_t *n_k = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    int64_t *s1_k = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    int32_t *hits = (int32_t *)calloc((size_t)V, sizeof(int32_t));
+    or_bsc_stats s;
+    memset(&s, 0, sizeof s);
+    /* step 1 and the bin sums of step 2 */
+    for (int64_t i = 0; i < h->n; ++i) {
+        bin[i] = or_bin_of(h, i, p);
+        if (bin[i] < 0) continue;
+        wq[i] = llrint((double)h->wepl[i] * 1024.0);
+        n[bin[i]] += 1;
+        s1[bin[i]] += wq[i];
+        s2[bin[i]] += (__int128)wq[i] * wq[i];
+        ++s.n_binned;
+    }
+    /* step 2: the cut */
+    for (int64_t i = 0; i < h->n; ++i) {
+        const int64_t b = bin[i];
+        if (b < 0) continue;
+        const __int128 dev = (__int128)n[b] * wq[i] - s1[b];
+        const __int128 var = (__int128)n[b] * s2[b] - (__int128)s1[b] * s1[b];
+        if (k2 > 0 && dev * dev > k2 * var) {
+            ++s.n_cut;
+            continue;
+        }
+        n_k[b] += 1;
+        s1_k[b] += wq[i];
+    }
+    /* step 3: carve the lines of the bins that missed the object */
+    int64_t used = 0, ncarved = 0, nskip = 0, visits = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : used, ncarved, nskip, visits)
+    for (int64_t b = 0; b < nb; ++b) {
+        if (n[b] > 0) ++used;
+        if (!(n_k[b] > 0 && s1_k[b] < e_q * n_k[b])) continue;
+        ++ncarved;
+        const int32_t iu = (int32_t)(b % p->nu), iv = (int32_t)((b / p->nu) % p->nv);
+        const int32_t k = (int32_t)(b / ((int64_t)p->nu * p->nv));
+        int32_t qin[3], qout[3];
+        if (or_bsc_line(p, g, k, iu, iv, qin, qout) != OR_OK) { ++nskip; continue; }
+        const int64_t P0[3] = {qin[0], qin[1], qin[2]};
+        const int64_t D[3] = {(int64_t)qout[0] - qin[0], (int64_t)qout[1] - qin[1],
+                              (int64_t)qout[2] - qin[2]};
+        visits += or_cells(P0, D, g, 0, NULL, 0, hits);
+    }
+    s.n_bins_used = used;
+    s.n_bins_carved = ncarved;
+    s.n_lines_skipped = nskip;
+    s.n_visits = visits;
+    /* step 4 */
+    uint8_t *cv = carved ? carved : (uint8_t *)malloc((size_t)(V > 0 ? V : 1));
+    for (int64_t v = 0; v < V; ++v) cv[v] = (uint8_t)(hits[v] > 0);
+    if (mask) or_bsc_blur(cv, g, bp->window, bp->thr_num, bp->thr_den, mask);
+    if (kept_n)
+        for (int64_t b = 0; b < nb; ++b) kept_n[b] = (uint32_t)n_k[b];
+    if (kept_sum)
+        for (int64_t b = 0; b < nb; ++b) kept_sum[b] = s1_k[b];
+    if (st) *st = s;
+    if (!carved) free(cv);
+    free(bin); free(wq); free(n); free(s1); free(s2); free(n_k); free(s1_k); free(hits);
+    return 0;
+}
+
 /* Step 2 for histories [0, n): status per history (OR_OK or a skip reason)
  * and the quantised endpoints as [n][3]. */
 void or_quantize_all(const or_hist *h, const or_grid *g, int32_t *status, int32_t *qin,
@@ -642,4 +804,12 @@ int oracle_hull_fbp(const or_hist *h, const or_grid *g, const or_fbp_params *p, 
     if (!h || !g || !p || !image) return 1;
     or_fbp(h, g, p, NULL, image, mask);
     return 0;
+}
+
+int oracle_hull_sc_binned(const or_hist *h, const or_grid *g, const or_fbp_params *p,
+                          const or_bsc_params *bp, uint32_t *kept_n, int64_t *kept_sum,
+                          uint8_t *carved, uint8_t *mask, or_bsc_stats *st)
+{
+    if (!h || !g || !p || !bp || !mask) return 1;
+    return or_bsc(h, g, p, bp, kept_n, kept_sum, carved, mask, st);
 }
