@@ -121,7 +121,8 @@ enum hull_op {
     HULL_OP_SM = 2,
     HULL_OP_ALL = 3,
     HULL_OP_FBP = 4,
-    HULL_OP_COUNT_LINES = 5
+    HULL_OP_COUNT_LINES = 5,
+    HULL_OP_SC_BINNED = 6
 };
 
 /* All parameters of the one-pass call. The paper's values: wepl_low 1.0 mm
@@ -155,7 +156,8 @@ int hull_abi_version(void);
 const char *hull_strerror(int status);
 
 /* Device workspace (bytes, 256-byte aligned start expected) that `op` needs
- * for a grid and n histories (fbp may be NULL unless op is HULL_OP_FBP).
+ * for a grid and n histories (fbp may be NULL unless op is HULL_OP_FBP or
+ * HULL_OP_SC_BINNED, where it gives the bins).
  * Returns 0 when nothing is needed, or (size_t)-1 on invalid arguments. */
 size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n,
                             const hullmi_fbp_params *fbp);
@@ -199,6 +201,52 @@ int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
  * required) gets the RSP estimate, mask (may be NULL) = image >= threshold. */
 int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
              float *image, uint8_t *mask, void *ws, size_t ws_bytes, void *stream);
+
+/* Binned SC: SC as the paper ran it (Section 3.2, after Algorithm 1) with the
+ * data cuts of Section 2.2, on the FDK hull's bins (`bins`, as hull_fbp takes
+ * them; its threshold is not used).
+ *   1. Every history with finite fields, |WEPL| < 2^16 mm and x_out != x_in
+ *      that lands on the detector is binned exactly as in hull_fbp; its WEPL
+ *      enters the statistics as w_q = rint(WEPL * 1024) (1/1024 mm).
+ *   2. Data cut: with n, S1 = sum w_q and S2 = sum w_q^2 over the bin, a
+ *      history is dropped when (n w_q - S1)^2 > k^2 (n S2 - S1^2), i.e. when
+ *      it lies more than k population standard deviations from the bin mean
+ *      (k = params->cut_sigmas; 0 keeps every history). Integer-exact.
+ *   3. A bin whose kept histories have mean WEPL below E_L (kept sum <
+ *      rint(E_L * 1024) * kept count, at least one kept) carves its line: from
+ *      the source (-src_dist, 0, 0) through the bin centre (0, u0 + (iu + 0.5)
+ *      du, v0 + (iv + 0.5) dv) in the lab frame at gantry angle angle0 + k
+ *      dangle (FP32), moved to the object frame and rounded like a history;
+ *      carved[v] = 1 for every v of its A.
+ *   4. mask[v] = 1 iff den * (uncarved voxels of the W x W window around v in
+ *      its slice; voxels outside the grid count as carved) > num * W^2, which
+ *      keeps voxels whose window mean exceeds num/den (0.4 in the paper).
+ * Outputs (device): kept_n [n_angles][nv][nu] uint32 and kept_sum (int64,
+ * 1/1024 mm) per bin after the cut, carved uint8[V]; each may be NULL (the
+ * workspace then holds it). mask uint8[V] is required. stats (device, may be
+ * NULL) is overwritten. EINVAL also for a non-finite wepl_low or |wepl_low| >=
+ * 2^16, cut_sigmas outside [0, 64], an even window or one outside [1, 31],
+ * thr_den <= 0 or thr_num < 0. */
+typedef struct hullmi_bsc_params {
+    float wepl_low;           /* E_L, mm (1.0 in the paper) */
+    int32_t cut_sigmas;       /* k (3 in the paper), 0 = no data cuts */
+    int32_t window;           /* W, odd (5 in the paper) */
+    int32_t thr_num, thr_den; /* keep iff the window mean exceeds num/den (2/5) */
+} hullmi_bsc_params;
+
+typedef struct hullmi_bsc_stats {
+    int64_t n_binned;         /* histories that landed in a bin */
+    int64_t n_cut;            /* of those, dropped by the data cut */
+    int64_t n_bins_used;      /* bins with at least one history */
+    int64_t n_bins_carved;    /* bins taken as misses */
+    int64_t n_lines_skipped;  /* of those, lines out of range or degenerate */
+    int64_t n_visits;         /* sum of |A| over the carved lines */
+} hullmi_bsc_stats;
+
+int hull_sc_binned(const hullmi_histories *hist, const hullmi_grid *grid,
+                   const hullmi_fbp_params *bins, const hullmi_bsc_params *params,
+                   uint32_t *kept_n, int64_t *kept_sum, uint8_t *carved, uint8_t *mask,
+                   hullmi_bsc_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
 /* The accumulate step alone, for lines already in quantised object-frame form
  * (for example one line per bin): q_in and q_out are device arrays [n][3] of

@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "hull_binned.h"
+#include "hull_bsc.h"
 #include "hull_device.h"
 #include "hull_kernels.h"
 #include "hull_runtime.h"
@@ -458,6 +459,117 @@ int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     return launch_status();
 }
 
+bool bsc_ok(const hullmi_bsc_params *b)
+{
+    if (!b) return false;
+    if (!std::isfinite(b->wepl_low) || !(std::fabs(b->wepl_low) < 65536.0f)) return false;
+    if (b->cut_sigmas < 0 || b->cut_sigmas > 64) return false;
+    if (b->window < 1 || b->window > 31 || b->window % 2 == 0) return false;
+    return b->thr_den > 0 && b->thr_num >= 0;
+}
+
+// Workspace of the binned SC: the per-history records, the per-bin sums and
+// kept ranges, kept counts and sums, the carved volume and the counters
+// (the last three used when the caller passes no array of its own).
+BscWs bsc_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, int64_t n, void *base,
+                    size_t *bytes)
+{
+    BscWs w;
+    const size_t nb = (size_t)p->nu * p->nv * p->n_angles;
+    char *b = reinterpret_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t nbytes) {
+        char *q = b ? b + off : nullptr;
+        off += align_up(nbytes);
+        return q;
+    };
+    w.rec = reinterpret_cast<int2 *>(take((size_t)std::max<int64_t>(n, 1) * 8));
+    w.cnt = reinterpret_cast<unsigned *>(take(nb * 4));
+    w.s1 = reinterpret_cast<unsigned long long *>(take(nb * 8));
+    w.s2lo = reinterpret_cast<unsigned long long *>(take(nb * 8));
+    w.s2hi = reinterpret_cast<unsigned long long *>(take(nb * 8));
+    w.bnd = reinterpret_cast<int2 *>(take(nb * 8));
+    w.kept_n = reinterpret_cast<unsigned *>(take(nb * 4));
+    w.kept_s = reinterpret_cast<unsigned long long *>(take(nb * 8));
+    w.carved = reinterpret_cast<uint8_t *>(take((size_t)voxels(g)));
+    w.stats = reinterpret_cast<unsigned long long *>(take(kBscStatWords * 8));
+    w.nb = (int64_t)nb;
+    if (bytes) *bytes = off;
+    return w;
+}
+
+int bsc_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+             const hullmi_bsc_params *bp, uint32_t *kept_n, int64_t *kept_sum, uint8_t *carved,
+             uint8_t *mask, hullmi_bsc_stats *stats, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !bsc_ok(bp) || !mask)
+        return HULL_EINVAL;
+    size_t need = 0;
+    bsc_ws_layout(fbp, grid, hist->n, nullptr, &need);
+    if (!ws || ws_bytes < need) return HULL_ENOMEM;
+    BscWs w = bsc_ws_layout(fbp, grid, hist->n, ws, nullptr);
+    if (kept_n) w.kept_n = kept_n;
+    if (kept_sum) w.kept_s = reinterpret_cast<unsigned long long *>(kept_sum);
+    if (carved) w.carved = carved;
+    if (stats) w.stats = reinterpret_cast<unsigned long long *>(stats);
+    FbpDev p;
+    p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
+    p.u0 = fbp->u0_mm; p.v0 = fbp->v0_mm;
+    p.rdu = 1.0f / fbp->du_mm; p.rdv = 1.0f / fbp->dv_mm; p.rda = 1.0f / fbp->dangle_deg;
+    p.angle0 = fbp->angle0_deg; p.dangle = fbp->dangle_deg; p.threshold = fbp->threshold;
+    p.half_dth = 0.0f;
+    p.nu = fbp->nu; p.nv = fbp->nv; p.n_angles = fbp->n_angles;
+    const int plane = p.nu * p.nv;
+    const int64_t V = voxels(grid);
+    fill_u32(w.cnt, 0u, w.nb, s);
+    fill_u64(w.s1, 0ull, w.nb, s);
+    fill_u64(w.s2lo, 0ull, w.nb, s);
+    fill_u64(w.s2hi, 0ull, w.nb, s);
+    fill_u32(w.kept_n, 0u, w.nb, s);
+    fill_u64(w.kept_s, 0ull, w.nb, s);
+    k_fill_u8<<<(unsigned)std::min<int64_t>(blocks_for(V), 4096), kBlock, 0, s>>>(w.carved, 0, V);
+    fill_u64(w.stats, 0ull, kBscStatWords, s);
+    const DevProps dp = dev_props();
+    const int64_t n = hist->n;
+    if (n > 0) {
+        // chunks so that every resident block gets one, at most kBscMaxChunk
+        auto chunk_for = [&](const void *fn, size_t lds) {
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ, reinterpret_cast<const void *>(fn), kBscThreads, lds) != hipSuccess ||
+                occ < 1) {
+                (void)hipGetLastError();
+                occ = 1;
+            }
+            const int64_t want = std::min<int64_t>((int64_t)dp.cus * occ,
+                                                   (n + kBscThreads - 1) / kBscThreads);
+            return std::min<int64_t>((n + want - 1) / want, kBscMaxChunk);
+        };
+        const size_t lim_s = allow_max_lds(reinterpret_cast<const void *>(k_bsc_stats), dp.max_lds);
+        const size_t lds_s = (size_t)plane * 16;
+        const int use_lds = lds_s <= lim_s ? 1 : 0;
+        const int64_t cs = chunk_for(reinterpret_cast<const void *>(k_bsc_stats), use_lds ? lds_s : 0);
+        k_bsc_stats<<<(unsigned)((n + cs - 1) / cs), kBscThreads, use_lds ? lds_s : 0, s>>>(
+            *hist, p, w, cs, use_lds);
+        k_bsc_bounds<<<blocks_for(w.nb), kBlock, 0, s>>>(w, bp->cut_sigmas);
+        const size_t lim_c = allow_max_lds(reinterpret_cast<const void *>(k_bsc_cut), dp.max_lds);
+        const size_t plane_c = (size_t)plane * 8;
+        const int np = 2 * plane_c <= lim_c ? 2 : (plane_c <= lim_c ? 1 : 0);
+        const int64_t cc = chunk_for(reinterpret_cast<const void *>(k_bsc_cut), np * plane_c);
+        k_bsc_cut<<<(unsigned)((n + cc - 1) / cc), kBscThreads, np * plane_c, s>>>(w, n, plane, cc,
+                                                                                 np);
+    } else {
+        k_bsc_bounds<<<blocks_for(w.nb), kBlock, 0, s>>>(w, bp->cut_sigmas);
+    }
+    const long long e_q = std::llrint((double)bp->wepl_low * 1024.0);
+    k_bsc_carve<<<blocks_for(w.nb), kBlock, 0, s>>>(w, p, dev_grid(grid), e_q);
+    const int r = bp->window / 2;
+    k_bsc_blur<<<blocks_for(V), kBlock, 0, s>>>(w.carved, mask, grid->nx, grid->ny, grid->nz, r,
+                                                (long long)bp->thr_num * bp->window * bp->window,
+                                                bp->thr_den);
+    return launch_status();
+}
+
 size_t ws_bytes_of(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_params *fbp)
 {
     if (n < 0) return (size_t)-1;
@@ -476,6 +588,12 @@ size_t ws_bytes_of(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_
     case HULL_OP_FBP:
         if (!grid_ok(grid) || !fbp_ok(fbp)) return (size_t)-1;
         return fbp_ws_layout(fbp, grid, nullptr).bytes;
+    case HULL_OP_SC_BINNED: {
+        if (!grid_ok(grid) || !fbp_ok(fbp) || n > INT32_MAX) return (size_t)-1;
+        size_t bytes = 0;
+        bsc_ws_layout(fbp, grid, n, nullptr, &bytes);
+        return bytes;
+    }
     default:
         return (size_t)-1;
     }
@@ -626,6 +744,15 @@ int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
              float *image, uint8_t *mask, void *ws, size_t ws_bytes, void *stream)
 {
     return fbp_impl(hist, grid, fbp, image, mask, ws, ws_bytes, as_stream(stream));
+}
+
+int hull_sc_binned(const hullmi_histories *hist, const hullmi_grid *grid,
+                   const hullmi_fbp_params *bins, const hullmi_bsc_params *params,
+                   uint32_t *kept_n, int64_t *kept_sum, uint8_t *carved, uint8_t *mask,
+                   hullmi_bsc_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    return bsc_impl(hist, grid, bins, params, kept_n, kept_sum, carved, mask, stats, ws, ws_bytes,
+                    as_stream(stream));
 }
 
 int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n, const hullmi_grid *grid,

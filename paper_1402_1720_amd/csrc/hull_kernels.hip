@@ -17,6 +17,12 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -224,54 +230,6 @@ __global__ void k_sm_mask(const int *M, uint8_t *mask, int64_t V, int64_t seg_le
 
 // ---------------------------------------------------------------------------
 // FDK hull
-
-// Where a history's line crosses x = 0, decided in FP32: gantry angle bin k,
-// detector bin (iu, iv) and the WEPL in fixed point (2^-16 mm). False when the
-// history is not binned.
-__device__ __forceinline__ bool fbp_locate_vals(float xi, float yi, float zi, float xo, float yo,
-                                                float zo, float a, float w, const FbpDev &p, int &k,
-                                                int &iu, int &iv, long long &fx)
-{
-    if (!(isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
-          isfinite(zo) && isfinite(a) && isfinite(w)))
-        return false;
-    if (!(fabsf(w) < 65536.0f)) return false;
-    const float ddx = xo - xi;
-    if (ddx == 0.0f) return false;
-    const float r = (0.0f - xi) / ddx;
-    const float u = yi + r * (yo - yi);
-    const float v = zi + r * (zo - zi);
-    const float fa = (a - p.angle0) * p.rda;
-    const float fu = (u - p.u0) * p.rdu;
-    const float fv = (v - p.v0) * p.rdv;
-    if (!(fabsf(fa) < 1.0e9f)) return false;
-    if (!(fu >= 0.0f && fu < (float)p.nu && fv >= 0.0f && fv < (float)p.nv)) return false;
-    long long kk = (long long)rintf(fa) % p.n_angles;
-    if (kk < 0) kk += p.n_angles;
-    k = (int)kk;
-    iu = (int)floorf(fu);
-    iv = (int)floorf(fv);
-    fx = llrint((double)w * 65536.0);
-    return true;
-}
-
-__device__ __forceinline__ bool fbp_locate(const hullmi_histories &h, int64_t i, const FbpDev &p,
-                                           int &k, int &iu, int &iv, long long &fx)
-{
-    return fbp_locate_vals(h.x_in[i], h.y_in[i], h.z_in[i], h.x_out[i], h.y_out[i], h.z_out[i],
-                           h.angle_deg[i], h.wepl[i], p, k, iu, iv, fx);
-}
-
-// Angle bin of a history from its angle alone (-1 when it cannot be binned).
-__device__ __forceinline__ int fbp_angle_bin(float a, const FbpDev &p)
-{
-    if (!isfinite(a)) return -1;
-    const float fa = (a - p.angle0) * p.rda;
-    if (!(fabsf(fa) < 1.0e9f)) return -1;
-    long long kk = (long long)rintf(fa) % p.n_angles;
-    if (kk < 0) kk += p.n_angles;
-    return (int)kk;
-}
 
 // Bin each history; WEPL sums in fixed point so the result does not depend
 // on the order of the atomics. Used when a detector plane does not fit LDS.

@@ -22,7 +22,8 @@ HULL_MSC_COUNT, HULL_MSC_NEIGHBOR_DIFF = 0, 1
 HULL_SM_FRACTION, HULL_SM_MAX_SLOPE = 0, 1
 HULL_SCOPE_VOLUME, HULL_SCOPE_SLICE = 0, 1
 HULL_NBR_INPLANE4, HULL_NBR_SPATIAL6 = 0, 1
-HULL_OP_SC, HULL_OP_MSC, HULL_OP_SM, HULL_OP_ALL, HULL_OP_FBP, HULL_OP_COUNT_LINES = range(6)
+(HULL_OP_SC, HULL_OP_MSC, HULL_OP_SM, HULL_OP_ALL, HULL_OP_FBP, HULL_OP_COUNT_LINES,
+ HULL_OP_SC_BINNED) = range(7)
 
 FIELDS = ("x_in", "y_in", "z_in", "x_out", "y_out", "z_out", "angle_deg", "wepl")
 
@@ -55,6 +56,15 @@ class hullmi_fbp_params(ctypes.Structure):
 class hullmi_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n_low", "n_high", "n_skipped", "n_missed_grid",
                                                "n_visits_low", "n_visits_high")]
+
+
+class hullmi_bsc_params(ctypes.Structure):
+    _fields_ = [("wepl_low", ctypes.c_float), ("cut_sigmas", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("thr_num", ctypes.c_int32), ("thr_den", ctypes.c_int32)]
+
+
+BSC_STATS_FIELDS = ("n_binned", "n_cut", "n_bins_used", "n_bins_carved", "n_lines_skipped",
+                    "n_visits")
 
 
 _OUT_FIELDS = [("N", ctypes.c_void_p), ("M", ctypes.c_void_p), ("sc_mask", ctypes.c_void_p),
@@ -106,6 +116,7 @@ SIGNATURES = {
                  _P, _P, _SZ, _P], ctypes.c_int),
     "hull_all": ([_P, _P, _P, _P, _P, _P, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_fbp": ([_P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "hull_sc_binned": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_count_lines": ([_P, _P, _I64, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_quantize": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "hull_footprint_bytes": ([ctypes.c_int, _P, _I64, _P], _SZ),
@@ -345,6 +356,38 @@ def hull_fbp(hist: Histories, grid, fbp: hullmi_fbp_params, image: torch.Tensor,
                         _dev_ptr(image, torch.float32, V, "image", d),
                         _dev_ptr(mask, torch.uint8, V, "mask", d), wp, wn, _stream(stream))
     _check(rc, "hull_fbp")
+
+
+def make_bsc_params(wepl_low=1.0, cut_sigmas=3, window=5, thr_num=2, thr_den=5) -> hullmi_bsc_params:
+    """Binned SC parameters; the defaults are the paper's (Sections 2.2, 3.2)."""
+    return hullmi_bsc_params(wepl_low, cut_sigmas, window, thr_num, thr_den)
+
+
+def bsc_stats_dict(stats: torch.Tensor) -> Dict[str, int]:
+    return dict(zip(BSC_STATS_FIELDS, (int(x) for x in stats.cpu().tolist())))
+
+
+def hull_sc_binned(hist: Histories, grid, bins: hullmi_fbp_params, params: hullmi_bsc_params,
+                   mask: torch.Tensor, kept_n: Optional[torch.Tensor] = None,
+                   kept_sum: Optional[torch.Tensor] = None, carved: Optional[torch.Tensor] = None,
+                   stats: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                   stream=None):
+    g = make_grid(grid)
+    V = _voxels(g)
+    nb = int(bins.nu) * int(bins.nv) * int(bins.n_angles)
+    if ws is None:
+        ws = workspace(HULL_OP_SC_BINNED, g, hist.n, hist.device, bins)
+    wp, wn = _ws(ws)
+    d = hist.device
+    # kept counts are uint32 in the ABI; below 2^31 (n < 2^31) they read alike as int32
+    kn = _dev_ptr(kept_n, torch.int32, nb, "kept_n", d)
+    rc = lib().hull_sc_binned(ctypes.byref(hist.c), ctypes.byref(g), ctypes.byref(bins),
+                              ctypes.byref(params), kn,
+                              _dev_ptr(kept_sum, torch.int64, nb, "kept_sum", d),
+                              _dev_ptr(carved, torch.uint8, V, "carved", d),
+                              _dev_ptr(mask, torch.uint8, V, "mask", d),
+                              _dev_ptr(stats, torch.int64, 6, "stats", d), wp, wn, _stream(stream))
+    _check(rc, "hull_sc_binned")
 
 
 def hull_count_lines(q_in: torch.Tensor, q_out: torch.Tensor, grid, counts: torch.Tensor,

@@ -195,3 +195,33 @@ def test_server_argument_checks():
     assert L.hull_server_wait(None, 1, None, 0) == H.HULL_EINVAL
     assert L.hull_server_stats(None, None) == H.HULL_EINVAL
     assert L.hull_server_destroy(None) == H.HULL_OK
+
+
+def test_binned_sc_workspace_and_argument_checks():
+    L = H.lib()
+    g = _grid()
+    f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
+    nb = 300 * 22 * 180
+    ws = H.hull_workspace_bytes(H.HULL_OP_SC_BINNED, g, 1024, f)
+    # records, per-bin sums, ranges, kept sums, the carved volume
+    assert ws >= 8 * 1024 + nb * (4 + 8 + 8 + 8 + 8 + 4 + 8) + 8 * 8 * 4
+    assert H.hull_workspace_bytes(H.HULL_OP_SC_BINNED, g, 2048, f) - ws == 8 * 1024
+    with pytest.raises(H.HullError):
+        H.hull_workspace_bytes(H.HULL_OP_SC_BINNED, g, 100, None)
+    h = _hist()
+    good = H.make_bsc_params()
+
+    def call(p=good, mask=FAKE, wsn=1 << 40, hist=h, bins=f):
+        return L.hull_sc_binned(ctypes.byref(hist), ctypes.byref(g), ctypes.byref(bins),
+                                ctypes.byref(p), None, None, None, mask, None, FAKE, wsn, None)
+
+    assert call(wsn=H.hull_workspace_bytes(H.HULL_OP_SC_BINNED, g, 10, f) - 1) == H.HULL_ENOMEM
+    assert call(mask=None) == H.HULL_EINVAL
+    for bad in (H.make_bsc_params(window=4), H.make_bsc_params(window=33),
+                H.make_bsc_params(thr_den=0), H.make_bsc_params(thr_num=-1),
+                H.make_bsc_params(cut_sigmas=-1), H.make_bsc_params(cut_sigmas=65),
+                H.make_bsc_params(wepl_low=float("nan")), H.make_bsc_params(wepl_low=65536.0)):
+        assert call(p=bad) == H.HULL_EINVAL
+    assert call(hist=_hist(-1)) == H.HULL_EINVAL
+    bad_bins = H.hullmi_fbp_params(0.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
+    assert call(bins=bad_bins) == H.HULL_EINVAL
