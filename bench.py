@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="serve 2000 requests of up to 1e8 histories (minutes) instead of 300 of "
                          "up to 1e7")
+    ap.add_argument("--bsc-only", action="store_true",
+                    help="time the binned SC alone (for a profile of its kernels)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one 256 MiB device-to-device copy: the "
                          "known-size kernel that scales hardware byte counters")
@@ -274,6 +276,16 @@ def main():
     stream = torch.cuda.current_stream()
     side = torch.cuda.Stream(device=dev)   # default priority, like every stream here
     fork, join = torch.cuda.Event(), torch.cuda.Event()
+
+    if args.bsc_only:
+        bsc = H.make_bsc_params()
+        ws_bsc = H.workspace(H.HULL_OP_SC_BINNED, grid, n, dev, fbp)
+        bmask = torch.zeros(V, dtype=torch.uint8, device=dev)
+        ms = _timed_on(torch, stream, lambda: H.hull_sc_binned(hist, grid, fbp, bsc, bmask,
+                                                               ws=ws_bsc, stream=stream),
+                       args.steps)
+        print(json.dumps({"binned_sc_ms": ms, "histories_per_s": n / (ms * 1e-3)}), flush=True)
+        return
 
     def step():
         # the FDK hull and the counting pass are independent: FDK runs on a
@@ -336,6 +348,26 @@ def main():
                                    H.HULL_NBR_INPLANE4, M, sm, ws=ws_all, stream=stream), reps)
     t_fbp = timed(lambda: H.hull_fbp(hist, grid, fbp, image, fmask, ws=ws_fbp, stream=stream), reps)
 
+    # binned SC (the paper's own SC: per-bin 3-sigma WEPL cuts on the FDK
+    # bins, one carve line per bin whose kept mean is below 1 mm, 5 x 5 mean
+    # above 0.4) on the same resident scan
+    bsc = H.make_bsc_params(wepl_low=1.0, cut_sigmas=3, window=5, thr_num=2, thr_den=5)
+    nbins = int(fbp.nu) * int(fbp.nv) * int(fbp.n_angles)
+    ws_bsc = H.workspace(H.HULL_OP_SC_BINNED, grid, n, dev, fbp)
+    bmask = torch.zeros(V, dtype=torch.uint8, device=dev)
+    bstats = torch.zeros(6, dtype=torch.int64, device=dev)
+    t_bsc = timed(lambda: H.hull_sc_binned(hist, grid, fbp, bsc, bmask, stats=bstats, ws=ws_bsc,
+                                           stream=stream), reps)
+    bst = H.bsc_stats_dict(bstats)
+    # algorithmic HBM bytes of one call: per history the eight fields read once
+    # and its 8-byte (bin, w_q) record written and read back; per bin the sums
+    # written and read (28 B), the kept range written (8 B), the kept count
+    # and sum written and read (24 B), the range read by the cut (28 B with
+    # the sums it replaces); per voxel the carved flag written and read and
+    # the mask written
+    bsc_bytes = 48 * n + 88 * nbins + 3 * V
+    bsc_gbs = bsc_bytes / (t_bsc * 1e-3) / 1e9
+
     # algorithmic work of one walk launch: 6 int lane-ops per voxel visit
     achieved_tops = visits * OPS_PER_VISIT / (t_walk * 1e-3) / 1e12
     # algorithmic HBM bytes of one walk launch: every WEPL, the other seven
@@ -378,10 +410,19 @@ def main():
                      "peak": PEAK_INT_TOPS, "unit": "TOP/s", "frac": achieved_tops / PEAK_INT_TOPS,
                      "traffic": measured_traffic()},
         "cpu_baseline": None,
+        "binned_sc": {
+            "workload": "same scan; FDK bins 1 mm x 5 mm x 180 angles, 3-sigma WEPL cuts, carve "
+                        "bins with kept mean < 1 mm, 5x5 mean > 0.4",
+            "ms": t_bsc, "histories_per_s": n / (t_bsc * 1e-3), "bins": nbins,
+            "bins_used": bst["n_bins_used"], "bins_carved": bst["n_bins_carved"],
+            "histories_cut": bst["n_cut"], "voxel_visits": bst["n_visits"],
+            "roofline": {"bound": "hbm", "per_unit": "48 B per history + 88 B per bin + 3 B per voxel",
+                         "achieved": bsc_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": bsc_gbs / PEAK_HBM_GBS, "bytes": bsc_bytes}},
     }
 
     # free the single-scan buffers before the batch and serving figures
-    del hist, N, M, sc, msc, sm, fmask, image, ws_all, ws_fbp
+    del hist, N, M, sc, msc, sm, fmask, image, ws_all, ws_fbp, ws_bsc, bmask
     torch.cuda.empty_cache()
     if not args.no_batch:
         log("batch: 16 scans")

@@ -222,8 +222,8 @@ int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
  *      its slice; voxels outside the grid count as carved) > num * W^2, which
  *      keeps voxels whose window mean exceeds num/den (0.4 in the paper).
  * Outputs (device): kept_n [n_angles][nv][nu] uint32 and kept_sum (int64,
- * 1/1024 mm) per bin after the cut, carved uint8[V]; each may be NULL (the
- * workspace then holds it). mask uint8[V] is required. stats (device, may be
+ * 1/1024 mm) per bin after the cut (each may be NULL: the workspace then holds
+ * it), carved uint8[V] 0/1 (may be NULL). mask uint8[V] is required. stats (device, may be
  * NULL) is overwritten. EINVAL also for a non-finite wepl_low or |wepl_low| >=
  * 2^16, cut_sigmas outside [0, 64], an even window or one outside [1, 31],
  * thr_den <= 0 or thr_num < 0. */

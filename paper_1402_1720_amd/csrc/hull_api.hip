@@ -469,7 +469,7 @@ bool bsc_ok(const hullmi_bsc_params *b)
 }
 
 // Workspace of the binned SC: the per-history records, the per-bin sums and
-// kept ranges, kept counts and sums, the carved volume and the counters
+// kept ranges, kept counts and sums, the carved bit volume and the counters
 // (the last three used when the caller passes no array of its own).
 BscWs bsc_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, int64_t n, void *base,
                     size_t *bytes)
@@ -491,8 +491,11 @@ BscWs bsc_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, int64_t n,
     w.bnd = reinterpret_cast<int2 *>(take(nb * 8));
     w.kept_n = reinterpret_cast<unsigned *>(take(nb * 4));
     w.kept_s = reinterpret_cast<unsigned long long *>(take(nb * 8));
-    w.carved = reinterpret_cast<uint8_t *>(take((size_t)voxels(g)));
+    w.cbits = reinterpret_cast<unsigned *>(take((size_t)(voxels(g) + 31) / 32 * 4));
     w.stats = reinterpret_cast<unsigned long long *>(take(kBscStatWords * 8));
+    w.cs = reinterpret_cast<float2 *>(take((size_t)p->n_angles * 8));
+    w.list = reinterpret_cast<int *>(take(nb * 4));
+    w.nlist = reinterpret_cast<int *>(take(4));
     w.nb = (int64_t)nb;
     if (bytes) *bytes = off;
     return w;
@@ -510,7 +513,6 @@ int bsc_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     BscWs w = bsc_ws_layout(fbp, grid, hist->n, ws, nullptr);
     if (kept_n) w.kept_n = kept_n;
     if (kept_sum) w.kept_s = reinterpret_cast<unsigned long long *>(kept_sum);
-    if (carved) w.carved = carved;
     if (stats) w.stats = reinterpret_cast<unsigned long long *>(stats);
     FbpDev p;
     p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
@@ -521,52 +523,67 @@ int bsc_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     p.nu = fbp->nu; p.nv = fbp->nv; p.n_angles = fbp->n_angles;
     const int plane = p.nu * p.nv;
     const int64_t V = voxels(grid);
-    fill_u32(w.cnt, 0u, w.nb, s);
-    fill_u64(w.s1, 0ull, w.nb, s);
-    fill_u64(w.s2lo, 0ull, w.nb, s);
-    fill_u64(w.s2hi, 0ull, w.nb, s);
-    fill_u32(w.kept_n, 0u, w.nb, s);
-    fill_u64(w.kept_s, 0ull, w.nb, s);
-    k_fill_u8<<<(unsigned)std::min<int64_t>(blocks_for(V), 4096), kBlock, 0, s>>>(w.carved, 0, V);
-    fill_u64(w.stats, 0ull, kBscStatWords, s);
+    // one launch zeroes the sums, counters and the carved bit volume
+    const int64_t vwords = (V + 31) / 32;
+    k_bsc_clear<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(
+                      blocks_for(std::max<int64_t>(w.nb, vwords)), 2048)),
+                  kBlock, 0, s>>>(w, vwords);
     const DevProps dp = dev_props();
     const int64_t n = hist->n;
+    // per-bin passes: one block of kBscThreads per CU (or fewer for few bins)
+    const unsigned per_bin_blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(dp.cus, (w.nb + kBscThreads - 1) / kBscThreads));
     if (n > 0) {
-        // chunks so that every resident block gets one, at most kBscMaxChunk
-        auto chunk_for = [&](const void *fn, size_t lds) {
+        // the three history passes share one shape: LDS copies of one or two
+        // detector planes at 8 bytes per bin, chunks so that every resident
+        // block gets one (at most kBscMaxChunk histories each)
+        const size_t plane_lds = (size_t)plane * 8;
+        auto shape = [&](const void *fn, int &np, int64_t &chunk) {
+            const size_t lim = allow_max_lds(fn, dp.max_lds);
+            np = 2 * plane_lds <= lim ? 2 : (plane_lds <= lim ? 1 : 0);
             int occ = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &occ, reinterpret_cast<const void *>(fn), kBscThreads, lds) != hipSuccess ||
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBscThreads, np * plane_lds) !=
+                    hipSuccess ||
                 occ < 1) {
                 (void)hipGetLastError();
                 occ = 1;
             }
             const int64_t want = std::min<int64_t>((int64_t)dp.cus * occ,
                                                    (n + kBscThreads - 1) / kBscThreads);
-            return std::min<int64_t>((n + want - 1) / want, kBscMaxChunk);
+            chunk = std::min<int64_t>((n + want - 1) / want, kBscMaxChunk);
         };
-        const size_t lim_s = allow_max_lds(reinterpret_cast<const void *>(k_bsc_stats), dp.max_lds);
-        const size_t lds_s = (size_t)plane * 16;
-        const int use_lds = lds_s <= lim_s ? 1 : 0;
-        const int64_t cs = chunk_for(reinterpret_cast<const void *>(k_bsc_stats), use_lds ? lds_s : 0);
-        k_bsc_stats<<<(unsigned)((n + cs - 1) / cs), kBscThreads, use_lds ? lds_s : 0, s>>>(
-            *hist, p, w, cs, use_lds);
-        k_bsc_bounds<<<blocks_for(w.nb), kBlock, 0, s>>>(w, bp->cut_sigmas);
-        const size_t lim_c = allow_max_lds(reinterpret_cast<const void *>(k_bsc_cut), dp.max_lds);
-        const size_t plane_c = (size_t)plane * 8;
-        const int np = 2 * plane_c <= lim_c ? 2 : (plane_c <= lim_c ? 1 : 0);
-        const int64_t cc = chunk_for(reinterpret_cast<const void *>(k_bsc_cut), np * plane_c);
-        k_bsc_cut<<<(unsigned)((n + cc - 1) / cc), kBscThreads, np * plane_c, s>>>(w, n, plane, cc,
-                                                                                 np);
+        int np;
+        int64_t ch;
+        shape(reinterpret_cast<const void *>(k_bsc_stats), np, ch);
+        k_bsc_stats<<<(unsigned)((n + ch - 1) / ch), kBscThreads, np * plane_lds, s>>>(*hist, p, w,
+                                                                                       ch, np);
+        shape(reinterpret_cast<const void *>(k_bsc_squares), np, ch);
+        k_bsc_squares<<<(unsigned)((n + ch - 1) / ch), kBscThreads, np * plane_lds, s>>>(w, n, plane,
+                                                                                         ch, np);
+        k_bsc_bounds<<<per_bin_blocks, kBscThreads, 0, s>>>(w, bp->cut_sigmas);
+        shape(reinterpret_cast<const void *>(k_bsc_cut), np, ch);
+        k_bsc_cut<<<(unsigned)((n + ch - 1) / ch), kBscThreads, np * plane_lds, s>>>(w, n, plane, ch,
+                                                                                     np);
     } else {
-        k_bsc_bounds<<<blocks_for(w.nb), kBlock, 0, s>>>(w, bp->cut_sigmas);
+        k_bsc_bounds<<<per_bin_blocks, kBscThreads, 0, s>>>(w, bp->cut_sigmas);
     }
     const long long e_q = std::llrint((double)bp->wepl_low * 1024.0);
-    k_bsc_carve<<<blocks_for(w.nb), kBlock, 0, s>>>(w, p, dev_grid(grid), e_q);
+    k_bsc_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w, p);
+    // carve blocks: one per CU, each with an LDS bit window of all the LDS
+    // there is (at most the whole volume); when the volume does not fit, the
+    // carve list runs detector rows first so that each block's lines stay in
+    // a few slices
+    const size_t lim_v = allow_max_lds(reinterpret_cast<const void *>(k_bsc_carve), dp.max_lds);
+    const int lwords = (int)std::min<int64_t>((int64_t)(lim_v / 4), vwords);
+    k_bsc_select<<<per_bin_blocks, kBscThreads, 0, s>>>(w, p, e_q, lwords < vwords ? 1 : 0);
+    k_bsc_carve<<<per_bin_blocks, kCarveThreads, (size_t)lwords * 4, s>>>(w, p, dev_grid(grid),
+                                                                          lwords);
     const int r = bp->window / 2;
-    k_bsc_blur<<<blocks_for(V), kBlock, 0, s>>>(w.carved, mask, grid->nx, grid->ny, grid->nz, r,
-                                                (long long)bp->thr_num * bp->window * bp->window,
-                                                bp->thr_den);
+    const dim3 bgrid((unsigned)((grid->nx + kBlurTx - 1) / kBlurTx),
+                     (unsigned)((grid->ny + kBlurTy - 1) / kBlurTy), (unsigned)grid->nz);
+    k_bsc_blur<<<bgrid, dim3(kBlurTx, kBlurTy), 0, s>>>(
+        w.cbits, carved, mask, grid->nx, grid->ny, r, (long long)bp->thr_num * bp->window * bp->window,
+        bp->thr_den);
     return launch_status();
 }
 

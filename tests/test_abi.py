@@ -203,8 +203,8 @@ def test_binned_sc_workspace_and_argument_checks():
     f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
     nb = 300 * 22 * 180
     ws = H.hull_workspace_bytes(H.HULL_OP_SC_BINNED, g, 1024, f)
-    # records, per-bin sums, ranges, kept sums, the carved volume
-    assert ws >= 8 * 1024 + nb * (4 + 8 + 8 + 8 + 8 + 4 + 8) + 8 * 8 * 4
+    # records, per-bin sums, ranges, kept sums, carve list, the carved bits
+    assert ws >= 8 * 1024 + nb * (4 + 8 + 8 + 8 + 8 + 4 + 8 + 4) + 8 * 8 * 4 // 8
     assert H.hull_workspace_bytes(H.HULL_OP_SC_BINNED, g, 2048, f) - ws == 8 * 1024
     with pytest.raises(H.HullError):
         H.hull_workspace_bytes(H.HULL_OP_SC_BINNED, g, 100, None)
