@@ -130,6 +130,8 @@ def _lib():
             "oracle_hull_all": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "oracle_hull_fbp": ([P, P, P, P, P], ctypes.c_int),
             "or_bsc_line": ([P, P, i32, i32, i32, P, P], ctypes.c_int),
+            "or_bsc_cut": ([P, P, i32, P, P, P, P], None),
+            "or_fbp_cut": ([P, P, P, i32, P, P, P], i64),
             "or_bsc_blur": ([P, P, i32, i32, i32, P], None),
             "or_bsc": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "oracle_hull_sc_binned": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
@@ -327,6 +329,32 @@ def bsc_blur(carved: np.ndarray, grid: OrGrid, window: int = 5, thr_num: int = 2
     _lib().or_bsc_blur(_ptr(c), ctypes.byref(grid), int(window), int(thr_num), int(thr_den),
                        _ptr(mask))
     return mask
+
+
+def bsc_cut(hist, p: OrFbpParams, k: int = 3):
+    """(bin, keep, binned, cut): per history its bin (-1 when not binned) and
+    whether the data cut at k standard deviations keeps it."""
+    hv = _HistView(hist)
+    n = hv.c.n
+    b = np.empty(max(n, 1), np.int64)
+    keep = np.empty(max(n, 1), np.uint8)
+    nb, nc = ctypes.c_int64(0), ctypes.c_int64(0)
+    _lib().or_bsc_cut(ctypes.byref(hv.c), ctypes.byref(p), int(k), _ptr(b), _ptr(keep),
+                      ctypes.byref(nb), ctypes.byref(nc))
+    return b[:n], keep[:n].astype(bool), int(nb.value), int(nc.value)
+
+
+def fbp_cut(hist, grid: OrGrid, p: OrFbpParams, k: int = 3):
+    """FDK hull after the data cuts: (image FP64, mask, kept bin means, kept)."""
+    hv = _HistView(hist)
+    V = _vox(grid)
+    nb = int(p.n_angles) * int(p.nv) * int(p.nu)
+    proj, img, mask = np.zeros(nb), np.zeros(V), np.zeros(V, np.uint8)
+    kept = _lib().or_fbp_cut(ctypes.byref(hv.c), ctypes.byref(grid), ctypes.byref(p), int(k),
+                             _ptr(proj), _ptr(img), _ptr(mask))
+    if kept < 0:
+        raise ValueError("FDK after cuts rejected its arguments")
+    return img, mask, proj, int(kept)
 
 
 def sc_binned(hist, grid: OrGrid, p: OrFbpParams, bp: Optional[OrBscParams] = None):

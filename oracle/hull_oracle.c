@@ -633,6 +633,42 @@ void or_bsc_blur(const uint8_t *carved, const or_grid *g, int32_t W, int32_t num
             }
 }
 
+/* Steps 1 and 2 for histories [0, n): bin[i] (-1 when not binned) and
+ * keep[i] (binned and not more than k standard deviations from its bin's
+ * mean; every binned history when k = 0). Adds to *binned and *cut. */
+void or_bsc_cut(const or_hist *h, const or_fbp_params *p, int32_t k, int64_t *bin, uint8_t *keep,
+                int64_t *binned, int64_t *cut)
+{
+    const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
+    const __int128 k2 = (__int128)k * k;
+    int64_t *n = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    int64_t *s1 = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    __int128 *s2 = (__int128 *)calloc((size_t)nb, sizeof(__int128));
+    int64_t *wq = (int64_t *)malloc((size_t)(h->n > 0 ? h->n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < h->n; ++i) {
+        keep[i] = 0;
+        bin[i] = or_bin_of(h, i, p);
+        if (bin[i] < 0) continue;
+        wq[i] = llrint((double)h->wepl[i] * 1024.0);
+        n[bin[i]] += 1;
+        s1[bin[i]] += wq[i];
+        s2[bin[i]] += (__int128)wq[i] * wq[i];
+        ++*binned;
+    }
+    for (int64_t i = 0; i < h->n; ++i) {
+        const int64_t b = bin[i];
+        if (b < 0) continue;
+        const __int128 dev = (__int128)n[b] * wq[i] - s1[b];
+        const __int128 var = (__int128)n[b] * s2[b] - (__int128)s1[b] * s1[b];
+        if (k2 > 0 && dev * dev > k2 * var) {
+            ++*cut;
+            continue;
+        }
+        keep[i] = 1;
+    }
+    free(n); free(s1); free(s2); free(wq);
+}
+
 /* Steps 1-4. kept_n, kept_sum (both [n_angles][nv][nu], sums in 1/1024 mm),
  * carved and mask may each be NULL. Returns 0, or 1 for a bad argument. */
 int or_bsc(const or_hist *h, const or_grid *g, const or_fbp_params *p, const or_bsc_params *bp,
@@ -643,40 +679,22 @@ int or_bsc(const or_hist *h, const or_grid *g, const or_fbp_params *p, const or_
     if (bp->window < 1 || bp->window % 2 == 0 || bp->thr_den <= 0) return 1;
     const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
     const int64_t V = (int64_t)g->nx * g->ny * g->nz;
-    const __int128 k2 = (__int128)bp->cut_sigmas * bp->cut_sigmas;
     const int64_t e_q = llrint((double)bp->wepl_low * 1024.0);
     int64_t *bin = (int64_t *)malloc((size_t)(h->n > 0 ? h->n : 1) * sizeof(int64_t));
-    int64_t *wq = (int64_t *)malloc((size_t)(h->n > 0 ? h->n : 1) * sizeof(int64_t));
+    uint8_t *keep = (uint8_t *)malloc((size_t)(h->n > 0 ? h->n : 1));
     int64_t *n = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
-    int64_t *s1 = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
-    __int128 *s2 = (__int128 *)calloc((size_t)nb, sizeof(__int128));
     int64_t *n_k = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
     int64_t *s1_k = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
     int32_t *hits = (int32_t *)calloc((size_t)V, sizeof(int32_t));
     or_bsc_stats s;
     memset(&s, 0, sizeof s);
-    /* step 1 and the bin sums of step 2 */
+    or_bsc_cut(h, p, bp->cut_sigmas, bin, keep, &s.n_binned, &s.n_cut);
     for (int64_t i = 0; i < h->n; ++i) {
-        bin[i] = or_bin_of(h, i, p);
         if (bin[i] < 0) continue;
-        wq[i] = llrint((double)h->wepl[i] * 1024.0);
-        n[bin[i]] += 1;
-        s1[bin[i]] += wq[i];
-        s2[bin[i]] += (__int128)wq[i] * wq[i];
-        ++s.n_binned;
-    }
-    /* step 2: the cut */
-    for (int64_t i = 0; i < h->n; ++i) {
-        const int64_t b = bin[i];
-        if (b < 0) continue;
-        const __int128 dev = (__int128)n[b] * wq[i] - s1[b];
-        const __int128 var = (__int128)n[b] * s2[b] - (__int128)s1[b] * s1[b];
-        if (k2 > 0 && dev * dev > k2 * var) {
-            ++s.n_cut;
-            continue;
-        }
-        n_k[b] += 1;
-        s1_k[b] += wq[i];
+        ++n[bin[i]];
+        if (!keep[i]) continue;
+        n_k[bin[i]] += 1;
+        s1_k[bin[i]] += llrint((double)h->wepl[i] * 1024.0);
     }
     /* step 3: carve the lines of the bins that missed the object */
     int64_t used = 0, ncarved = 0, nskip = 0, visits = 0;
@@ -708,8 +726,41 @@ int or_bsc(const or_hist *h, const or_grid *g, const or_fbp_params *p, const or_
         for (int64_t b = 0; b < nb; ++b) kept_sum[b] = s1_k[b];
     if (st) *st = s;
     if (!carved) free(cv);
-    free(bin); free(wq); free(n); free(s1); free(s2); free(n_k); free(s1_k); free(hits);
+    free(bin); free(keep); free(n); free(n_k); free(s1_k); free(hits);
     return 0;
+}
+
+/* FDK hull after the data cuts (Section 3.1: the FBP hull was computed from
+ * the histories left after the cuts of Section 2.2): the bins of step 1, the
+ * cut of step 2 (k standard deviations, k = 0 keeps all), then the FDK steps
+ * with each bin's mean WEPL taken over its kept histories (FP64; an empty bin
+ * is 0). proj (optional, [n_angles][nv][nu]) receives the kept bin means
+ * before weighting and filtering. Returns histories kept, or -1 for a bad k. */
+int64_t or_fbp_cut(const or_hist *h, const or_grid *g, const or_fbp_params *p, int32_t k,
+                   double *proj, double *image, uint8_t *mask)
+{
+    if (k < 0 || k > 64) return -1;
+    const int64_t nb = (int64_t)p->n_angles * p->nv * p->nu;
+    int64_t *bin = (int64_t *)malloc((size_t)(h->n > 0 ? h->n : 1) * sizeof(int64_t));
+    uint8_t *keep = (uint8_t *)malloc((size_t)(h->n > 0 ? h->n : 1));
+    double *q = (double *)calloc((size_t)nb, sizeof(double));
+    double *cnt = (double *)calloc((size_t)nb, sizeof(double));
+    int64_t binned = 0, cut = 0;
+    or_bsc_cut(h, p, k, bin, keep, &binned, &cut);
+    for (int64_t i = 0; i < h->n; ++i) {
+        if (bin[i] < 0 || !keep[i]) continue;
+        q[bin[i]] += (double)h->wepl[i];
+        cnt[bin[i]] += 1.0;
+    }
+    for (int64_t b = 0; b < nb; ++b) q[b] = cnt[b] > 0.0 ? q[b] / cnt[b] : 0.0;
+    if (proj) memcpy(proj, q, (size_t)nb * sizeof(double));
+    or_fbp_filter(p, q);
+    or_fbp_backproject(g, p, q, image);
+    const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+    if (mask)
+        for (int64_t v = 0; v < V; ++v) mask[v] = (uint8_t)(image[v] >= (double)p->threshold);
+    free(bin); free(keep); free(q); free(cnt);
+    return binned - cut;
 }
 
 /* Step 2 for histories [0, n): status per history (OR_OK or a skip reason)

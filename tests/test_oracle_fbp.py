@@ -159,3 +159,45 @@ def test_fdk_hull_of_the_head_phantom():
     mid.reshape(32, 200, 200)[8:24] = True
     assert mask[core & mid].mean() > 0.99
     assert mask[(truth == 0) & mid].mean() < 0.02
+
+
+def test_cuts_off_is_the_plain_fdk_hull():
+    spec = gen.config_spec(1, n_hist=40_000)
+    h = gen.generate(spec)
+    P = oracle.fbp_params(spec.fbp_geometry(du=1.0, dv=2.5))
+    G = oracle.grid_of(spec.grid)
+    img, mask, proj, used = oracle.fbp(h, G, P)
+    img0, mask0, _, kept = oracle.fbp_cut(h, G, P, k=0)
+    assert kept == used
+    assert np.array_equal(img, img0) and np.array_equal(mask, mask0)
+
+
+def test_cuts_remove_outliers_from_the_fdk_hull():
+    """Twelve histories per bin along each bin-centre ray of a uniform sphere:
+    eleven carry the sphere's chord, and in a third of the bins the twelfth
+    carries a far outlier (+150 mm). With n = 12 one outlier x among equal
+    values v lies 11|x - v|/12 from the mean while 3 sigma is
+    3 sqrt(11)|x - v|/12, so the cut drops exactly the outliers and leaves
+    the equal values (0.083|x - v| from the mean): the hull after the cuts is
+    the clean scan's, and without cuts the outliers spoil it."""
+    R = 30.0
+    geo, h = _bin_centre_rays(1e7, R, nu=90, nv=18, n_angles=180)
+    grid = gen.Grid((64, 64, 8), (1.0, 1.0, 2.0))
+    G = oracle.grid_of(grid)
+    P = oracle.fbp_params(geo)
+    clean_img, clean_mask, _, _ = oracle.fbp(h, G, P)
+    rng = np.random.default_rng(7)
+    reps = {k: np.repeat(v, 12) for k, v in h.items()}
+    bad = rng.random(len(h["wepl"])) < 1 / 3
+    w = reps["wepl"].reshape(-1, 12).copy()
+    w[bad, 11] += np.float32(150.0)
+    reps["wepl"] = w.reshape(-1)
+    img, mask, proj, kept = oracle.fbp_cut(reps, G, P, k=3)
+    assert kept == len(reps["wepl"]) - int(bad.sum())
+    assert np.abs(img - clean_img).max() < 1e-9
+    assert np.array_equal(mask, clean_mask)
+    raw, raw_mask, _, _ = oracle.fbp(reps, G, P)
+    assert np.abs(raw - clean_img).max() > 0.5
+    b, keep, binned, cut = oracle.bsc_cut(reps, P, 3)
+    assert binned == len(reps["wepl"]) and cut == int(bad.sum())
+    assert np.array_equal(~keep.reshape(-1, 12)[:, 11], bad)
