@@ -359,6 +359,10 @@ def main():
     t_bsc = timed(lambda: H.hull_sc_binned(hist, grid, fbp, bsc, bmask, stats=bstats, ws=ws_bsc,
                                            stream=stream), reps)
     bst = H.bsc_stats_dict(bstats)
+    # FDK hull after the same 3-sigma cuts
+    ws_fcut = H.workspace(H.HULL_OP_FBP_CUT, grid, n, dev, fbp)
+    t_fcut = timed(lambda: H.hull_fbp_cut(hist, grid, fbp, 3, image, fmask, ws=ws_fcut,
+                                          stream=stream), reps)
     # algorithmic HBM bytes of one call: per history the eight fields read once
     # and its 8-byte (bin, w_q) record written and read back; per bin the sums
     # written and read (28 B), the kept range written (8 B), the kept count
@@ -395,7 +399,8 @@ def main():
                    "histories": n, "grid": list(grid.n), "angles": spec.n_angles},
         "per_rule_histories_per_s": {
             "sc": n / (t_sc * 1e-3), "msc": n / (t_msc * 1e-3), "sm": n / (t_sm * 1e-3),
-            "all_one_pass": n / (t_all * 1e-3), "fbp": n / (t_fbp * 1e-3)},
+            "all_one_pass": n / (t_all * 1e-3), "fbp": n / (t_fbp * 1e-3),
+            "sc_binned": n / (t_bsc * 1e-3), "fbp_after_cuts": n / (t_fcut * 1e-3)},
         "latency_ms": {"p50": float(np.percentile(per_step, 50)),
                        "p99": float(np.percentile(per_step, 99))},
         "walk": {"ms": t_walk, "voxel_visits": visits, "visits_per_s": visits / (t_walk * 1e-3),
@@ -422,7 +427,7 @@ def main():
     }
 
     # free the single-scan buffers before the batch and serving figures
-    del hist, N, M, sc, msc, sm, fmask, image, ws_all, ws_fbp, ws_bsc, bmask
+    del hist, N, M, sc, msc, sm, fmask, image, ws_all, ws_fbp, ws_bsc, bmask, ws_fcut
     torch.cuda.empty_cache()
     if not args.no_batch:
         log("batch: 16 scans")

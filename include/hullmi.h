@@ -122,7 +122,8 @@ enum hull_op {
     HULL_OP_ALL = 3,
     HULL_OP_FBP = 4,
     HULL_OP_COUNT_LINES = 5,
-    HULL_OP_SC_BINNED = 6
+    HULL_OP_SC_BINNED = 6,
+    HULL_OP_FBP_CUT = 7
 };
 
 /* All parameters of the one-pass call. The paper's values: wepl_low 1.0 mm
@@ -156,8 +157,8 @@ int hull_abi_version(void);
 const char *hull_strerror(int status);
 
 /* Device workspace (bytes, 256-byte aligned start expected) that `op` needs
- * for a grid and n histories (fbp may be NULL unless op is HULL_OP_FBP or
- * HULL_OP_SC_BINNED, where it gives the bins).
+ * for a grid and n histories (fbp may be NULL unless op is HULL_OP_FBP,
+ * HULL_OP_FBP_CUT or HULL_OP_SC_BINNED, where it gives the bins).
  * Returns 0 when nothing is needed, or (size_t)-1 on invalid arguments. */
 size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n,
                             const hullmi_fbp_params *fbp);
@@ -201,6 +202,18 @@ int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
  * required) gets the RSP estimate, mask (may be NULL) = image >= threshold. */
 int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
              float *image, uint8_t *mask, void *ws, size_t ws_bytes, void *stream);
+
+/* FDK hull after the data cuts (Section 3.1 computes its FBP hull from the
+ * histories that survive the cuts of Section 2.2): histories are binned as in
+ * hull_fbp, each bin drops its histories more than cut_sigmas population
+ * standard deviations from its mean WEPL (decided exactly on WEPL in 1/1024
+ * mm, as hull_sc_binned does; 0 keeps all), and the bin means are taken over
+ * the kept histories (WEPL summed in 2^-16 mm, as hull_fbp sums it); then the
+ * FDK steps of hull_fbp. EINVAL also for cut_sigmas outside [0, 64].
+ * Workspace: op HULL_OP_FBP_CUT. */
+int hull_fbp_cut(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+                 int32_t cut_sigmas, float *image, uint8_t *mask, void *ws, size_t ws_bytes,
+                 void *stream);
 
 /* Binned SC: SC as the paper ran it (Section 3.2, after Algorithm 1) with the
  * data cuts of Section 2.2, on the FDK hull's bins (`bins`, as hull_fbp takes

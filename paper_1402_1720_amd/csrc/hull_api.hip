@@ -405,13 +405,8 @@ int all_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     return rc;
 }
 
-int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
-             float *image, uint8_t *mask, void *ws, size_t ws_bytes, hipStream_t s)
+FbpDev fbp_dev(const hullmi_fbp_params *fbp)
 {
-    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image) return HULL_EINVAL;
-    const size_t need = fbp_ws_layout(fbp, grid, nullptr).bytes;
-    if (!ws || ws_bytes < need) return HULL_ENOMEM;
-    FbpWs w = fbp_ws_layout(fbp, grid, ws);
     FbpDev p;
     p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
     p.u0 = fbp->u0_mm; p.v0 = fbp->v0_mm;
@@ -419,6 +414,48 @@ int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     p.angle0 = fbp->angle0_deg; p.dangle = fbp->dangle_deg; p.threshold = fbp->threshold;
     p.half_dth = (float)(0.5 * (double)fbp->dangle_deg * 3.14159265358979323846 / 180.0);
     p.nu = fbp->nu; p.nv = fbp->nv; p.n_angles = fbp->n_angles;
+    return p;
+}
+
+// Weighting, filtering and backprojection of per-bin sums (fixed point of
+// `unit` mm) and counts: the FDK steps after the binning.
+void fbp_reconstruct(const hullmi_grid *grid, const FbpDev &p, const FbpWs &w,
+                     const unsigned long long *sum, const unsigned *cnt, double unit, float *image,
+                     uint8_t *mask, hipStream_t s)
+{
+    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(double);
+    fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
+    k_fbp_filter<<<(unsigned)(p.n_angles * p.nv), kBlock, lds, s>>>(sum, cnt, w.q, p, unit);
+    k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
+    FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
+                  grid->x0, grid->y0, grid->z0};
+    int ntx, nty, ntz;
+    const int64_t ntiles = bp_tiles(grid, ntx, nty, ntz);
+    k_fbp_footprint<<<blocks_for(ntiles * p.n_angles), kBlock, 0, s>>>(w.cs, p, gd, w.fp, ntx, nty,
+                                                                       ntz);
+    k_fbp_backproject_tiles<<<(unsigned)ntiles, kBpTile * kBpTile, 0, s>>>(w.q, w.cs, w.fp, p, gd,
+                                                                          image, mask, ntx, nty);
+}
+
+void fbp_bin_stage(const hullmi_histories *hist, const FbpDev &p, const FbpWs &w, hipStream_t s);
+
+int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+             float *image, uint8_t *mask, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image) return HULL_EINVAL;
+    const size_t need = fbp_ws_layout(fbp, grid, nullptr).bytes;
+    if (!ws || ws_bytes < need) return HULL_ENOMEM;
+    FbpWs w = fbp_ws_layout(fbp, grid, ws);
+    const FbpDev p = fbp_dev(fbp);
+    fbp_bin_stage(hist, p, w, s);
+    fbp_reconstruct(grid, p, w, w.sum, w.cnt, 1.0 / 65536.0, image, mask, s);
+    return launch_status();
+}
+
+// Zeroes the FDK bin sums and counts and bins the histories into them (WEPL
+// in 2^-16 mm).
+void fbp_bin_stage(const hullmi_histories *hist, const FbpDev &p, const FbpWs &w, hipStream_t s)
+{
     const int64_t nb = (int64_t)p.nu * p.nv * p.n_angles;
     fill_u64(w.sum, 0ull, nb, s);
     fill_u32(w.cnt, 0u, nb, s);
@@ -444,19 +481,6 @@ int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
             k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
         }
     }
-    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(double);
-    fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
-    k_fbp_filter<<<(unsigned)(p.n_angles * p.nv), kBlock, lds, s>>>(w.sum, w.cnt, w.q, p);
-    k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
-    FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
-                  grid->x0, grid->y0, grid->z0};
-    int ntx, nty, ntz;
-    const int64_t ntiles = bp_tiles(grid, ntx, nty, ntz);
-    k_fbp_footprint<<<blocks_for(ntiles * p.n_angles), kBlock, 0, s>>>(w.cs, p, gd, w.fp, ntx, nty,
-                                                                       ntz);
-    k_fbp_backproject_tiles<<<(unsigned)ntiles, kBpTile * kBpTile, 0, s>>>(w.q, w.cs, w.fp, p, gd,
-                                                                          image, mask, ntx, nty);
-    return launch_status();
 }
 
 bool bsc_ok(const hullmi_bsc_params *b)
@@ -501,34 +525,20 @@ BscWs bsc_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, int64_t n,
     return w;
 }
 
-int bsc_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
-             const hullmi_bsc_params *bp, uint32_t *kept_n, int64_t *kept_sum, uint8_t *carved,
-             uint8_t *mask, hullmi_bsc_stats *stats, void *ws, size_t ws_bytes, hipStream_t s)
+
+// The data-cut stage shared by the binned SC and the FDK hull after cuts:
+// zero the per-bin sums, counters, statistics and `vwords` words of the
+// carved bit volume, then bin (stats), sum squares, find the kept ranges
+// (bounds) and sum the kept histories (cut). Returns the block count of the
+// per-bin passes.
+unsigned bsc_cut_stage(const hullmi_histories *hist, const FbpDev &p, BscWs &w, int ksig,
+                       int64_t vwords, const DevProps &dp, hipStream_t s,
+                       unsigned long long *fsum = nullptr, unsigned *fcnt = nullptr)
 {
-    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !bsc_ok(bp) || !mask)
-        return HULL_EINVAL;
-    size_t need = 0;
-    bsc_ws_layout(fbp, grid, hist->n, nullptr, &need);
-    if (!ws || ws_bytes < need) return HULL_ENOMEM;
-    BscWs w = bsc_ws_layout(fbp, grid, hist->n, ws, nullptr);
-    if (kept_n) w.kept_n = kept_n;
-    if (kept_sum) w.kept_s = reinterpret_cast<unsigned long long *>(kept_sum);
-    if (stats) w.stats = reinterpret_cast<unsigned long long *>(stats);
-    FbpDev p;
-    p.src_dist = fbp->src_dist_mm; p.du = fbp->du_mm; p.dv = fbp->dv_mm;
-    p.u0 = fbp->u0_mm; p.v0 = fbp->v0_mm;
-    p.rdu = 1.0f / fbp->du_mm; p.rdv = 1.0f / fbp->dv_mm; p.rda = 1.0f / fbp->dangle_deg;
-    p.angle0 = fbp->angle0_deg; p.dangle = fbp->dangle_deg; p.threshold = fbp->threshold;
-    p.half_dth = 0.0f;
-    p.nu = fbp->nu; p.nv = fbp->nv; p.n_angles = fbp->n_angles;
     const int plane = p.nu * p.nv;
-    const int64_t V = voxels(grid);
-    // one launch zeroes the sums, counters and the carved bit volume
-    const int64_t vwords = (V + 31) / 32;
     k_bsc_clear<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(
                       blocks_for(std::max<int64_t>(w.nb, vwords)), 2048)),
                   kBlock, 0, s>>>(w, vwords);
-    const DevProps dp = dev_props();
     const int64_t n = hist->n;
     // per-bin passes: one block of kBscThreads per CU (or fewer for few bins)
     const unsigned per_bin_blocks = (unsigned)std::max<int64_t>(
@@ -560,13 +570,34 @@ int bsc_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
         shape(reinterpret_cast<const void *>(k_bsc_squares), np, ch);
         k_bsc_squares<<<(unsigned)((n + ch - 1) / ch), kBscThreads, np * plane_lds, s>>>(w, n, plane,
                                                                                          ch, np);
-        k_bsc_bounds<<<per_bin_blocks, kBscThreads, 0, s>>>(w, bp->cut_sigmas);
+        k_bsc_bounds<<<per_bin_blocks, kBscThreads, 0, s>>>(w, ksig);
         shape(reinterpret_cast<const void *>(k_bsc_cut), np, ch);
-        k_bsc_cut<<<(unsigned)((n + ch - 1) / ch), kBscThreads, np * plane_lds, s>>>(w, n, plane, ch,
-                                                                                     np);
+        k_bsc_cut<<<(unsigned)((n + ch - 1) / ch), kBscThreads, np * plane_lds, s>>>(
+            w, n, plane, ch, np, hist->wepl, fsum, fcnt);
     } else {
-        k_bsc_bounds<<<per_bin_blocks, kBscThreads, 0, s>>>(w, bp->cut_sigmas);
+        k_bsc_bounds<<<per_bin_blocks, kBscThreads, 0, s>>>(w, ksig);
     }
+    return per_bin_blocks;
+}
+
+int bsc_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+             const hullmi_bsc_params *bp, uint32_t *kept_n, int64_t *kept_sum, uint8_t *carved,
+             uint8_t *mask, hullmi_bsc_stats *stats, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !bsc_ok(bp) || !mask)
+        return HULL_EINVAL;
+    size_t need = 0;
+    bsc_ws_layout(fbp, grid, hist->n, nullptr, &need);
+    if (!ws || ws_bytes < need) return HULL_ENOMEM;
+    BscWs w = bsc_ws_layout(fbp, grid, hist->n, ws, nullptr);
+    if (kept_n) w.kept_n = kept_n;
+    if (kept_sum) w.kept_s = reinterpret_cast<unsigned long long *>(kept_sum);
+    if (stats) w.stats = reinterpret_cast<unsigned long long *>(stats);
+    const FbpDev p = fbp_dev(fbp);
+    const int64_t V = voxels(grid);
+    const int64_t vwords = (V + 31) / 32;
+    const DevProps dp = dev_props();
+    const unsigned per_bin_blocks = bsc_cut_stage(hist, p, w, bp->cut_sigmas, vwords, dp, s);
     const long long e_q = std::llrint((double)bp->wepl_low * 1024.0);
     k_bsc_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w, p);
     // carve blocks: one per CU, each with an LDS bit window of all the LDS
@@ -584,6 +615,36 @@ int bsc_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     k_bsc_blur<<<bgrid, dim3(kBlurTx, kBlurTy), 0, s>>>(
         w.cbits, carved, mask, grid->nx, grid->ny, r, (long long)bp->thr_num * bp->window * bp->window,
         bp->thr_den);
+    return launch_status();
+}
+
+// Workspace of the FDK hull after cuts: the cut stage's, then the FDK steps'.
+size_t fbp_cut_ws_bytes(const hullmi_fbp_params *fbp, const hullmi_grid *g, int64_t n, size_t *cut)
+{
+    size_t b = 0;
+    bsc_ws_layout(fbp, g, n, nullptr, &b);
+    if (cut) *cut = align_up(b);
+    return align_up(b) + fbp_ws_layout(fbp, g, nullptr).bytes;
+}
+
+int fbp_cut_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+                 int32_t cut_sigmas, float *image, uint8_t *mask, void *ws, size_t ws_bytes,
+                 hipStream_t s)
+{
+    if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image || cut_sigmas < 0 ||
+        cut_sigmas > 64)
+        return HULL_EINVAL;
+    size_t cut = 0;
+    const size_t need = fbp_cut_ws_bytes(fbp, grid, hist->n, &cut);
+    if (!ws || ws_bytes < need) return HULL_ENOMEM;
+    BscWs w = bsc_ws_layout(fbp, grid, hist->n, ws, nullptr);
+    const FbpWs f = fbp_ws_layout(fbp, grid, reinterpret_cast<char *>(ws) + cut);
+    const FbpDev p = fbp_dev(fbp);
+    // the FDK bins of every history (2^-16 mm sums), then the cut stage takes
+    // the cut histories out of them
+    fbp_bin_stage(hist, p, f, s);
+    bsc_cut_stage(hist, p, w, cut_sigmas, 0, dev_props(), s, f.sum, f.cnt);
+    fbp_reconstruct(grid, p, f, f.sum, f.cnt, 1.0 / 65536.0, image, mask, s);
     return launch_status();
 }
 
@@ -605,6 +666,9 @@ size_t ws_bytes_of(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_
     case HULL_OP_FBP:
         if (!grid_ok(grid) || !fbp_ok(fbp)) return (size_t)-1;
         return fbp_ws_layout(fbp, grid, nullptr).bytes;
+    case HULL_OP_FBP_CUT:
+        if (!grid_ok(grid) || !fbp_ok(fbp) || n > INT32_MAX) return (size_t)-1;
+        return fbp_cut_ws_bytes(fbp, grid, n, nullptr);
     case HULL_OP_SC_BINNED: {
         if (!grid_ok(grid) || !fbp_ok(fbp) || n > INT32_MAX) return (size_t)-1;
         size_t bytes = 0;
@@ -770,6 +834,13 @@ int hull_sc_binned(const hullmi_histories *hist, const hullmi_grid *grid,
 {
     return bsc_impl(hist, grid, bins, params, kept_n, kept_sum, carved, mask, stats, ws, ws_bytes,
                     as_stream(stream));
+}
+
+int hull_fbp_cut(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
+                 int32_t cut_sigmas, float *image, uint8_t *mask, void *ws, size_t ws_bytes,
+                 void *stream)
+{
+    return fbp_cut_impl(hist, grid, fbp, cut_sigmas, image, mask, ws, ws_bytes, as_stream(stream));
 }
 
 int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n, const hullmi_grid *grid,

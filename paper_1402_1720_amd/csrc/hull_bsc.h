@@ -63,7 +63,8 @@ struct BscWs {
 __global__ void k_bsc_stats(hullmi_histories h, FbpDev p, BscWs w, int64_t chunk, int nplanes);
 __global__ void k_bsc_squares(BscWs w, int64_t n, int plane, int64_t chunk, int nplanes);
 __global__ void k_bsc_bounds(BscWs w, int ksig);
-__global__ void k_bsc_cut(BscWs w, int64_t n, int plane, int64_t chunk, int nplanes);
+__global__ void k_bsc_cut(BscWs w, int64_t n, int plane, int64_t chunk, int nplanes,
+                          const float *wepl, unsigned long long *fsum, unsigned *fcnt);
 __global__ void k_bsc_trig(BscWs w, FbpDev p);
 __global__ void k_bsc_select(BscWs w, FbpDev p, long long e_q, int row_first);
 __global__ void k_bsc_carve(BscWs w, FbpDev p, DevGrid g, int lwords);

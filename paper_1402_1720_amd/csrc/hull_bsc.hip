@@ -300,9 +300,12 @@ __global__ void __launch_bounds__(kBscThreads) k_bsc_bounds(BscWs w, int ksig)
 
 // Pass 4. The records of a chunk are tested against their bin's kept range;
 // kept ones are summed in the LDS planes of the chunk's first and last record
-// (nplanes 2, or only the first), the rest directly.
+// (nplanes 2, or only the first), the rest directly. With fsum set (the FDK
+// hull after cuts) each cut history is also taken out of the FDK bin sums
+// (WEPL in 2^-16 mm, from wepl) and counts.
 __global__ void __launch_bounds__(kBscThreads)
-k_bsc_cut(BscWs w, int64_t n, int plane, int64_t chunk, int nplanes)
+k_bsc_cut(BscWs w, int64_t n, int plane, int64_t chunk, int nplanes, const float *wepl,
+          unsigned long long *fsum, unsigned *fcnt)
 {
     extern __shared__ unsigned long long lk[];
     const int64_t base = (int64_t)blockIdx.x * chunk;
@@ -332,6 +335,11 @@ k_bsc_cut(BscWs w, int64_t n, int plane, int64_t chunk, int nplanes)
             if (r.x < 0) continue;
             if (r.y < bd[u].x || r.y > bd[u].y) {
                 ++ncut;
+                if (fsum) {
+                    const long long fx = llrint((double)wepl[i0 + (int64_t)u * blockDim.x] * 65536.0);
+                    atomicAdd(fsum + r.x, (unsigned long long)(-fx));
+                    atomicAdd(fcnt + r.x, 0xffffffffu);
+                }
                 continue;
             }
             if (narrow(r.y) && p0 >= 0 && r.x >= p0 && r.x < p0 + plane) {

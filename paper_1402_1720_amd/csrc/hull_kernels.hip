@@ -308,12 +308,13 @@ k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *c
     }
 }
 
-// One block per detector row: bin means, cosine pre-weight, then the
+// One block per detector row: bin means (sums in fixed point of `unit` mm),
+// cosine pre-weight, then the
 // Shepp-Logan convolution along u (FP64 accumulation in the order j = 0 ..
 // nu - 1, rows taken as zero outside the detector).
 constexpr int kFilterOut = 4;
 __global__ void __launch_bounds__(256)
-k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p)
+k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p, double unit)
 {
     extern __shared__ double sh[];
     const int nu = p.nu;
@@ -327,7 +328,7 @@ k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDe
     for (int iu = threadIdx.x; iu < nu; iu += blockDim.x) {
         const int64_t b = r * nu + iu;
         const unsigned c = cnt[b];
-        const double mean = c ? (double)(long long)sum[b] * (1.0 / 65536.0) / (double)c : 0.0;
+        const double mean = c ? (double)(long long)sum[b] * unit / (double)c : 0.0;
         const double uc = (double)p.u0 + ((double)iu + 0.5) * du;
         row[iu] = mean * D / sqrt(D * D + uc * uc + vc * vc);
     }

@@ -23,7 +23,7 @@ HULL_SM_FRACTION, HULL_SM_MAX_SLOPE = 0, 1
 HULL_SCOPE_VOLUME, HULL_SCOPE_SLICE = 0, 1
 HULL_NBR_INPLANE4, HULL_NBR_SPATIAL6 = 0, 1
 (HULL_OP_SC, HULL_OP_MSC, HULL_OP_SM, HULL_OP_ALL, HULL_OP_FBP, HULL_OP_COUNT_LINES,
- HULL_OP_SC_BINNED) = range(7)
+ HULL_OP_SC_BINNED, HULL_OP_FBP_CUT) = range(8)
 
 FIELDS = ("x_in", "y_in", "z_in", "x_out", "y_out", "z_out", "angle_deg", "wepl")
 
@@ -117,6 +117,7 @@ SIGNATURES = {
     "hull_all": ([_P, _P, _P, _P, _P, _P, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_fbp": ([_P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_sc_binned": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "hull_fbp_cut": ([_P, _P, _P, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_count_lines": ([_P, _P, _I64, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_quantize": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "hull_footprint_bytes": ([ctypes.c_int, _P, _I64, _P], _SZ),
@@ -356,6 +357,21 @@ def hull_fbp(hist: Histories, grid, fbp: hullmi_fbp_params, image: torch.Tensor,
                         _dev_ptr(image, torch.float32, V, "image", d),
                         _dev_ptr(mask, torch.uint8, V, "mask", d), wp, wn, _stream(stream))
     _check(rc, "hull_fbp")
+
+
+def hull_fbp_cut(hist: Histories, grid, fbp: hullmi_fbp_params, cut_sigmas: int,
+                 image: torch.Tensor, mask: Optional[torch.Tensor] = None,
+                 ws: Optional[torch.Tensor] = None, stream=None):
+    g = make_grid(grid)
+    V = _voxels(g)
+    if ws is None:
+        ws = workspace(HULL_OP_FBP_CUT, g, hist.n, hist.device, fbp)
+    wp, wn = _ws(ws)
+    d = hist.device
+    rc = lib().hull_fbp_cut(ctypes.byref(hist.c), ctypes.byref(g), ctypes.byref(fbp),
+                            int(cut_sigmas), _dev_ptr(image, torch.float32, V, "image", d),
+                            _dev_ptr(mask, torch.uint8, V, "mask", d), wp, wn, _stream(stream))
+    _check(rc, "hull_fbp_cut")
 
 
 def make_bsc_params(wepl_low=1.0, cut_sigmas=3, window=5, thr_num=2, thr_den=5) -> hullmi_bsc_params:

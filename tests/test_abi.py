@@ -225,3 +225,20 @@ def test_binned_sc_workspace_and_argument_checks():
     assert call(hist=_hist(-1)) == H.HULL_EINVAL
     bad_bins = H.hullmi_fbp_params(0.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
     assert call(bins=bad_bins) == H.HULL_EINVAL
+
+
+def test_fbp_cut_workspace_and_argument_checks():
+    L = H.lib()
+    g = _grid()
+    f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
+    ws = H.hull_workspace_bytes(H.HULL_OP_FBP_CUT, g, 1024, f)
+    assert ws >= H.hull_workspace_bytes(H.HULL_OP_FBP, g, 1024, f) + 8 * 1024
+    h = _hist()
+
+    def call(k=3, image=FAKE, wsn=1 << 40):
+        return L.hull_fbp_cut(ctypes.byref(h), ctypes.byref(g), ctypes.byref(f), k, image, None,
+                              FAKE, wsn, None)
+
+    assert call(k=-1) == H.HULL_EINVAL and call(k=65) == H.HULL_EINVAL
+    assert call(image=None) == H.HULL_EINVAL
+    assert call(wsn=H.hull_workspace_bytes(H.HULL_OP_FBP_CUT, g, 10, f) - 1) == H.HULL_ENOMEM

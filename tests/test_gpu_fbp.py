@@ -89,3 +89,56 @@ def test_fbp_fine_detectors_take_the_fallback_paths(du, dv, path):
         assert 80 * 1024 < plane_bytes <= 160 * 1024
     img, mask, ref, rmask = _run(h, g, geo)
     _check(img, mask, ref, rmask, geo.threshold)
+
+
+# ---------------------------------------------------------------------------
+# FDK hull after the data cuts
+
+def _run_cut(h, grid, geo, k):
+    V = grid.voxels
+    img = torch.zeros(V, dtype=torch.float32, device=DEV)
+    mask = torch.zeros(V, dtype=torch.uint8, device=DEV)
+    H.hull_fbp_cut(H.Histories.from_numpy(h, DEV), grid, H.make_fbp_params(geo), k, img, mask)
+    torch.cuda.synchronize()
+    ref, rmask, _, _ = oracle.fbp_cut(h, oracle.grid_of(grid), oracle.fbp_params(geo), k)
+    return img.cpu().numpy().astype(np.float64), mask.cpu().numpy(), ref, rmask
+
+
+def _with_outliers(h, frac, seed):
+    h = {k: v.copy() for k, v in h.items()}
+    rng = np.random.default_rng(seed)
+    bad = rng.random(h["wepl"].size) < frac
+    h["wepl"][bad] = rng.uniform(0.0, 300.0, int(bad.sum())).astype(np.float32)
+    return h
+
+
+@pytest.mark.parametrize("k", [3, 0, 1])
+def test_fbp_cut_config2_with_outliers(k):
+    """The benchmark scan with 2% uniform outliers: FP32 image within 1e-4 of
+    the FP64 oracle's after the same exact cuts."""
+    spec = gen.config_spec(2)
+    h = _with_outliers(gen.generate(spec), 0.02, 0x5EED00C7)
+    geo = spec.fbp_geometry(du=1.0, dv=5.0)
+    img, mask, ref, rmask = _run_cut(h, spec.grid, geo, k)
+    err = _check(img, mask, ref, rmask, geo.threshold)
+    print("config2 FDK after cuts, k", k, "max rel err", err, flush=True)
+
+
+def test_fbp_cut_sphere_outliers_and_fallbacks():
+    """One far outlier in a third of the bins of a sphere scan (the cut removes
+    exactly those), and fine bins whose planes do not fit the LDS."""
+    geo, h = _bin_centre_rays(150.0, 30.0, nu=160, nv=12, n_angles=360)
+    reps = {k: np.repeat(v, 12) for k, v in h.items()}
+    rng = np.random.default_rng(9)
+    w = reps["wepl"].reshape(-1, 12).copy()
+    w[rng.random(w.shape[0]) < 1 / 3, 11] += np.float32(150.0)
+    reps["wepl"] = w.reshape(-1)
+    grid = gen.Grid((64, 64, 4), (1.0, 1.0, 1.0))
+    img, mask, ref, rmask = _run_cut(reps, grid, geo, 3)
+    _check(img, mask, ref, rmask, geo.threshold)
+    g = gen.Grid((32, 32, 16), (1.0, 1.0, 2.5))
+    spec = gen.ScanSpec(g, 200_000, 36, gen.head_phantom(g), 0x5EED0111, sigma=1.0)
+    hh = _with_outliers(gen.generate(spec), 0.05, 3)
+    for du, dv in ((0.2, 0.8), (0.1, 0.5)):
+        img, mask, ref, rmask = _run_cut(hh, g, spec.fbp_geometry(du=du, dv=dv), 3)
+        _check(img, mask, ref, rmask, 0.6)
