@@ -286,6 +286,54 @@ size_t hull_footprint_bytes(int op, const hullmi_grid *grid, int64_t n,
                             const hullmi_fbp_params *fbp);
 
 /* ------------------------------------------------------------------------
+ * Sessions: online accumulation.
+ *
+ * MSC and SM need no binning, so each path can be carved as soon as it is
+ * measured, during the scan, with the hull available right after it
+ * (Section 5). A session keeps N and M resident on one device and adds chunks
+ * of histories to them as they arrive; the masks of all three rules can be
+ * read at any time and equal those of one call over every history pushed so
+ * far (counts are integers, so the order and chunking of pushes do not
+ * matter). Pushed chunks are appended to a device buffer of
+ * max(max_chunk, 2^22) histories; a full buffer is counted while the next
+ * chunks fill a second one, and a read counts what is buffered, so the
+ * session's rate stays near that of one call over the whole scan however
+ * small the chunks. A session owns its device memory (counts, masks, the two
+ * buffers and a workspace, allocated at creation) and two streams of default
+ * priority. Calls on one session serialise; sessions are independent.
+ * ---------------------------------------------------------------------- */
+
+typedef struct hullmi_session hullmi_session;
+
+/* New session for a grid and the rules' parameters (hullmi_params, checked as
+ * hull_all checks them), for chunks of at most max_chunk (1 .. 2^31 - 1)
+ * histories, on HIP device `device`. EINVAL for bad arguments, ENOMEM when the
+ * device memory cannot be allocated. */
+int hull_session_create(const hullmi_grid *grid, const hullmi_params *params, int64_t max_chunk,
+                        int device, hullmi_session **out);
+
+/* Adds a chunk (n <= max_chunk) of histories: its eight arrays are host
+ * memory (host = 1; pinned memory copies fastest) or device memory (host = 0,
+ * already written). They are copied into the session's buffer, while earlier
+ * chunks are counted, and the call returns once the copy is done: the caller
+ * may then reuse the arrays. */
+int hull_session_push(hullmi_session *s, const hullmi_histories *chunk, int host);
+
+/* Counts what is buffered, waits for every count so far, computes the masks
+ * asked for and copies the
+ * asked-for outputs (each may be NULL): N, M (int32[V]), the SC, MSC and SM
+ * masks (uint8[V]) and the accumulated counters. host = 1: the outputs are
+ * host memory, else device memory. Returns when they are written. */
+int hull_session_read(hullmi_session *s, int32_t *N, int32_t *M, uint8_t *sc_mask,
+                      uint8_t *msc_mask, uint8_t *sm_mask, hullmi_stats *stats, int host);
+
+/* Zeroes the counts and counters (a new scan). */
+int hull_session_reset(hullmi_session *s);
+
+/* Waits for pending work and frees the session. */
+int hull_session_destroy(hullmi_session *s);
+
+/* ------------------------------------------------------------------------
  * Batches: many scans, planned once and launched as one unit.
  *
  * The scans are independent (every history is its own line, Section 3), so a

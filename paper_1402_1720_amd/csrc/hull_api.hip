@@ -682,7 +682,48 @@ size_t ws_bytes_of(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_
 
 }  // namespace
 
-// ---- shared with the batch and server runtime ----
+// ---- shared with the batch, server and session runtime ----
+
+size_t rules_ws_bytes(const hullmi_grid *g) { return sm_ws_bytes(g); }
+
+size_t counting_ws_bytes(const hullmi_grid *g, int64_t n) { return counts_ws_bytes(g, n); }
+
+bool params_ok(const hullmi_params *p)
+{
+    return p && std::isfinite(p->wepl_low) && std::isfinite(p->wepl_high) &&
+           msc_args_ok(p->msc_n_t, p->msc_mode, p->nbr) &&
+           sm_args_ok(p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr);
+}
+
+bool grid_valid(const hullmi_grid *g) { return grid_ok(g); }
+
+bool hist_valid(const hullmi_histories *h) { return hist_ok(h); }
+
+int masks_from_counts(const hullmi_grid *g, const hullmi_params *p, const int32_t *N,
+                      const int32_t *M, uint8_t *sc, uint8_t *msc, uint8_t *sm, void *ws,
+                      hipStream_t s)
+{
+    if (sc) k_sc_mask<<<blocks_for(voxels(g)), kBlock, 0, s>>>(N, sc, voxels(g));
+    int rc = launch_status();
+    if (rc == HULL_OK) rc = run_msc_mask(g, N, msc, p->msc_n_t, p->msc_mode, p->nbr, s);
+    if (rc == HULL_OK)
+        rc = run_sm_mask(g, M, sm, p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr,
+                         ws, s);
+    return rc;
+}
+
+int counts_accumulate(const hullmi_histories *h, const hullmi_grid *g, const hullmi_params *p,
+                      int32_t *N, int32_t *M, hullmi_stats *stats, void *ws, hipStream_t s)
+{
+    return run_counts(h, g, p->wepl_low, p->wepl_high, N, M, HULL_ACCUMULATE, stats, ws, s, 0);
+}
+
+void zero_counts(int32_t *N, int32_t *M, hullmi_stats *stats, int64_t V, hipStream_t s)
+{
+    fill_u32(N, 0u, V, s);
+    fill_u32(M, 0u, V, s);
+    fill_u64(stats, 0ull, (int64_t)(sizeof(hullmi_stats) / 8), s);
+}
 
 size_t job_ws_bytes(const hullmi_job &j)
 {

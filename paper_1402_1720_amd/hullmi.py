@@ -131,6 +131,12 @@ SIGNATURES = {
     "hull_server_wait": ([_P, ctypes.c_uint64, _P, _I64], ctypes.c_int),
     "hull_server_stats": ([_P, _P], ctypes.c_int),
     "hull_server_destroy": ([_P], ctypes.c_int),
+    "hull_session_create": ([_P, _P, _I64, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
+                            ctypes.c_int),
+    "hull_session_push": ([_P, _P, ctypes.c_int], ctypes.c_int),
+    "hull_session_read": ([_P, _P, _P, _P, _P, _P, _P, ctypes.c_int], ctypes.c_int),
+    "hull_session_reset": ([_P], ctypes.c_int),
+    "hull_session_destroy": ([_P], ctypes.c_int),
 }
 
 _lib_handle = None
@@ -584,6 +590,73 @@ class Server:
             lib().hull_server_destroy(self._h)
             self._h = None
             self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Session:
+    """Online accumulation (``hull_session_*``): counts resident on the device,
+    chunks pushed as they arrive, masks read on demand."""
+
+    def __init__(self, grid, params: hullmi_params, max_chunk: int, device: int = 0):
+        self.grid = make_grid(grid)
+        self.V = _voxels(self.grid)
+        self.params = params
+        self.max_chunk = int(max_chunk)
+        h = ctypes.c_void_p()
+        _check(lib().hull_session_create(ctypes.byref(self.grid), ctypes.byref(params),
+                                         self.max_chunk, int(device), ctypes.byref(h)),
+               "hull_session_create")
+        self._h = h
+
+    def push(self, chunk) -> None:
+        """``chunk``: a ``Histories`` (device) or a dict of eight host arrays
+        (numpy float32, or CPU torch tensors, ideally pinned)."""
+        if isinstance(chunk, Histories):
+            _check(lib().hull_session_push(self._h, ctypes.byref(chunk.c), 0), "hull_session_push")
+            return
+        arrs = {}
+        for k in FIELDS:
+            a = chunk[k]
+            if isinstance(a, torch.Tensor):
+                if a.is_cuda or a.dtype != torch.float32 or not a.is_contiguous():
+                    raise ValueError(f"{k}: host float32 contiguous tensor expected")
+                arrs[k] = (a, a.data_ptr(), a.numel())
+            else:
+                import numpy as np
+                a = np.ascontiguousarray(a, dtype=np.float32)
+                arrs[k] = (a, a.ctypes.data, a.size)
+        n = arrs["wepl"][2]
+        if any(v[2] != n for v in arrs.values()):
+            raise ValueError("chunk arrays differ in length")
+        c = hullmi_histories(*[arrs[k][1] if n else None for k in FIELDS], n)
+        _check(lib().hull_session_push(self._h, ctypes.byref(c), 1), "hull_session_push")
+
+    def read(self, counts: bool = True, masks: bool = True) -> Dict[str, object]:
+        """Host copies of N, M, the three masks and the counters so far."""
+        import numpy as np
+        V = self.V
+        N = np.empty(V, np.int32) if counts else None
+        M = np.empty(V, np.int32) if counts else None
+        m = [np.empty(V, np.uint8) if masks else None for _ in range(3)]
+        st = hullmi_stats()
+        p = lambda a: None if a is None else ctypes.c_void_p(a.ctypes.data)
+        _check(lib().hull_session_read(self._h, p(N), p(M), p(m[0]), p(m[1]), p(m[2]),
+                                       ctypes.byref(st), 1), "hull_session_read")
+        return dict(N=N, M=M, sc=m[0], msc=m[1], sm=m[2],
+                    stats={k: int(getattr(st, k)) for k in STATS_FIELDS})
+
+    def reset(self) -> None:
+        _check(lib().hull_session_reset(self._h), "hull_session_reset")
+
+    def close(self) -> None:
+        if self._h:
+            lib().hull_session_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

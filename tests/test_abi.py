@@ -242,3 +242,23 @@ def test_fbp_cut_workspace_and_argument_checks():
     assert call(k=-1) == H.HULL_EINVAL and call(k=65) == H.HULL_EINVAL
     assert call(image=None) == H.HULL_EINVAL
     assert call(wsn=H.hull_workspace_bytes(H.HULL_OP_FBP_CUT, g, 10, f) - 1) == H.HULL_ENOMEM
+
+
+def test_session_argument_checks():
+    L = H.lib()
+    g, p = _grid(), H.make_params()
+    out = ctypes.c_void_p()
+    assert L.hull_session_create(ctypes.byref(g), ctypes.byref(p), 1000, 0, None) == H.HULL_EINVAL
+    assert L.hull_session_create(ctypes.byref(_grid(nx=0)), ctypes.byref(p), 1000, 0,
+                                 ctypes.byref(out)) == H.HULL_EINVAL
+    assert L.hull_session_create(ctypes.byref(g), ctypes.byref(p), 0, 0,
+                                 ctypes.byref(out)) == H.HULL_EINVAL
+    bad = H.make_params(msc_n_t=0)
+    assert L.hull_session_create(ctypes.byref(g), ctypes.byref(bad), 1000, 0,
+                                 ctypes.byref(out)) == H.HULL_EINVAL
+    assert not out.value
+    h = _hist()
+    assert L.hull_session_push(None, ctypes.byref(h), 1) == H.HULL_EINVAL
+    assert L.hull_session_read(None, None, None, None, None, None, None, 1) == H.HULL_EINVAL
+    assert L.hull_session_reset(None) == H.HULL_EINVAL
+    assert L.hull_session_destroy(None) == H.HULL_EINVAL
