@@ -25,7 +25,7 @@ ORACLE_CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contra
 
 OK, SKIP_NONFINITE, SKIP_RANGE, SKIP_DEGENERATE = 0, 1, 2, 3
 MSC_COUNT, MSC_NEIGHBOR_DIFF = 0, 1
-SM_FRACTION, SM_MAX_SLOPE = 0, 1
+SM_FRACTION, SM_MAX_SLOPE, SM_EDGE = 0, 1, 2
 SCOPE_VOLUME, SCOPE_SLICE = 0, 1
 NBR_INPLANE4, NBR_SPATIAL6 = 0, 1
 

@@ -315,7 +315,7 @@ void or_counts(const or_hist *h, const or_grid *g, float e_low, float e_high,
 /* Step 5: hull rules.                                                       */
 
 enum { OR_MSC_COUNT = 0, OR_MSC_NEIGHBOR_DIFF = 1 };
-enum { OR_SM_FRACTION = 0, OR_SM_MAX_SLOPE = 1 };
+enum { OR_SM_FRACTION = 0, OR_SM_MAX_SLOPE = 1, OR_SM_EDGE = 2 };
 enum { OR_SCOPE_VOLUME = 0, OR_SCOPE_SLICE = 1 };
 enum { OR_NBR_INPLANE4 = 0, OR_NBR_SPATIAL6 = 1 };
 
@@ -373,9 +373,100 @@ int or_msc(const int32_t *N, const or_grid *g, int32_t n_t, int mode, int nbr, u
  * With scope SLICE each z-slice gets its own statistic (the paper thresholds
  * slice by slice, Section 3.4). mt_out (optional) receives M_t per slice (or
  * once) for MAX_SLOPE and max M for FRACTION. Returns 0 or -1. */
+/* SM threshold from the strongest edge of M in one slice (Section 3.4: the
+ * edge with the largest gradient of M is found in each slice and the largest
+ * M on it is the slice's threshold; voxels with M >= M_t are kept). The paper
+ * used an unstated modification of Canny's detector; this one is stated in
+ * full and is integer-exact:
+ *   gradient  Sobel: gx = [M(i+1,j-1) + 2M(i+1,j) + M(i+1,j+1)]
+ *                       - [M(i-1,j-1) + 2M(i-1,j) + M(i-1,j+1)], gy likewise
+ *             along j; G = |gx| + |gy| for 1 <= i <= nx-2, 1 <= j <= ny-2,
+ *             G = 0 on the slice border;
+ *   direction d = (1,0) if 5|gy| <= 2|gx|, (0,1) if 5|gx| <= 2|gy|, else (1,1)
+ *             when gx and gy have the same sign and (1,-1) otherwise;
+ *   thinning  p is an edge pixel iff G(p) > 0, G(p) > G(p - d), G(p) >= G(p + d)
+ *             (G = 0 outside the slice);
+ *   the edge  seed = the edge pixel of largest G (ties: largest index); the
+ *             edge is the 8-connected set of edge pixels q with
+ *             den G(q) >= num G(seed) that contains the seed;
+ *   threshold M_t = max of M over the edge; mask = [M >= M_t]; a slice
+ *             without edge pixels keeps nothing.
+ * Writes the slice's mask and returns M_t (-1 when there is no edge). */
+static int64_t or_sm_edge_slice(const int32_t *M, int64_t nx, int64_t ny, int32_t num, int32_t den,
+                                 uint8_t *mask)
+{
+    const int64_t P = nx * ny;
+    int64_t *G = (int64_t *)calloc((size_t)P, sizeof(int64_t));
+    int8_t *dir = (int8_t *)calloc((size_t)P, 1);
+    uint8_t *edge = (uint8_t *)calloc((size_t)P, 1);
+    uint8_t *seen = (uint8_t *)calloc((size_t)P, 1);
+    int64_t *stack = (int64_t *)malloc((size_t)P * sizeof(int64_t));
+#define AT(i, j) ((int64_t)M[(j) * nx + (i)])
+    for (int64_t j = 1; j + 1 < ny; ++j)
+        for (int64_t i = 1; i + 1 < nx; ++i) {
+            const int64_t gx = (AT(i + 1, j - 1) + 2 * AT(i + 1, j) + AT(i + 1, j + 1)) -
+                               (AT(i - 1, j - 1) + 2 * AT(i - 1, j) + AT(i - 1, j + 1));
+            const int64_t gy = (AT(i - 1, j + 1) + 2 * AT(i, j + 1) + AT(i + 1, j + 1)) -
+                               (AT(i - 1, j - 1) + 2 * AT(i, j - 1) + AT(i + 1, j - 1));
+            const int64_t ax = llabs(gx), ay = llabs(gy);
+            G[j * nx + i] = ax + ay;
+            dir[j * nx + i] = 5 * ay <= 2 * ax ? 0 : (5 * ax <= 2 * ay ? 1 : ((gx > 0) == (gy > 0) ? 2 : 3));
+        }
+#undef AT
+    static const int DI[4] = {1, 0, 1, 1}, DJ[4] = {0, 1, 1, -1};
+    int64_t seed = -1;
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+            const int64_t p = j * nx + i;
+            if (G[p] <= 0) continue;
+            const int d = dir[p];
+            const int64_t ib = i - DI[d], jb = j - DJ[d], ia = i + DI[d], ja = j + DJ[d];
+            const int64_t gb = (ib >= 0 && ib < nx && jb >= 0 && jb < ny) ? G[jb * nx + ib] : 0;
+            const int64_t ga = (ia >= 0 && ia < nx && ja >= 0 && ja < ny) ? G[ja * nx + ia] : 0;
+            if (G[p] > gb && G[p] >= ga) {
+                edge[p] = 1;
+                if (seed < 0 || G[p] >= G[seed]) seed = p;
+            }
+        }
+    int64_t mt = -1;
+    if (seed >= 0) {
+        const int64_t gs = G[seed];
+        int64_t top = 0;
+        stack[top++] = seed;
+        seen[seed] = 1;
+        mt = M[seed];
+        while (top > 0) {
+            const int64_t p = stack[--top];
+            const int64_t i = p % nx, j = p / nx;
+            if (M[p] > mt) mt = M[p];
+            for (int64_t b = j - 1; b <= j + 1; ++b)
+                for (int64_t a = i - 1; a <= i + 1; ++a) {
+                    if (a < 0 || a >= nx || b < 0 || b >= ny) continue;
+                    const int64_t q = b * nx + a;
+                    if (seen[q] || !edge[q] || (int64_t)den * G[q] < (int64_t)num * gs) continue;
+                    seen[q] = 1;
+                    stack[top++] = q;
+                }
+        }
+    }
+    for (int64_t p = 0; p < P; ++p) mask[p] = (uint8_t)(mt >= 0 && (int64_t)M[p] >= mt);
+    free(G); free(dir); free(edge); free(seen); free(stack);
+    return mt;
+}
+
 int or_sm(const int32_t *M, const or_grid *g, int32_t num, int32_t den, int mode, int scope,
           int nbr, uint8_t *mask, int64_t *mt_out)
 {
+    if (mode == OR_SM_EDGE) {
+        /* per slice by definition; num / den is the edge's hysteresis fraction */
+        if (scope != OR_SCOPE_SLICE || den <= 0 || num < 0) return -1;
+        const int64_t plane = (int64_t)g->nx * g->ny;
+        for (int64_t k = 0; k < g->nz; ++k) {
+            const int64_t mt = or_sm_edge_slice(M + k * plane, g->nx, g->ny, num, den, mask + k * plane);
+            if (mt_out) mt_out[k] = mt;
+        }
+        return 0;
+    }
     const int64_t plane = (int64_t)g->nx * g->ny;
     const int64_t V = plane * g->nz;
     const int64_t nseg = scope == OR_SCOPE_SLICE ? g->nz : 1;
