@@ -385,6 +385,9 @@ def main():
     t_sm = timed(lambda: H.hull_sm(hist, grid, 5.0, 3, 5, H.HULL_SM_FRACTION, H.HULL_SCOPE_VOLUME,
                                    H.HULL_NBR_INPLANE4, M, sm, ws=ws_all, stream=stream), reps)
     t_fbp = timed(lambda: H.hull_fbp(hist, grid, fbp, image, fmask, ws=ws_fbp, stream=stream), reps)
+    # SM with the per-slice threshold from each slice's strongest edge
+    t_sm_edge = timed(lambda: H.hull_sm(hist, grid, 5.0, 1, 2, H.HULL_SM_EDGE, H.HULL_SCOPE_SLICE,
+                                        H.HULL_NBR_INPLANE4, M, sm, ws=ws_all, stream=stream), reps)
 
     # binned SC (the paper's own SC: per-bin 3-sigma WEPL cuts on the FDK
     # bins, one carve line per bin whose kept mean is below 1 mm, 5 x 5 mean
@@ -438,7 +441,8 @@ def main():
         "per_rule_histories_per_s": {
             "sc": n / (t_sc * 1e-3), "msc": n / (t_msc * 1e-3), "sm": n / (t_sm * 1e-3),
             "all_one_pass": n / (t_all * 1e-3), "fbp": n / (t_fbp * 1e-3),
-            "sc_binned": n / (t_bsc * 1e-3), "fbp_after_cuts": n / (t_fcut * 1e-3)},
+            "sc_binned": n / (t_bsc * 1e-3), "fbp_after_cuts": n / (t_fcut * 1e-3),
+            "sm_edge_threshold": n / (t_sm_edge * 1e-3)},
         "latency_ms": {"p50": float(np.percentile(per_step, 50)),
                        "p99": float(np.percentile(per_step, 99))},
         "walk": {"ms": t_walk, "voxel_visits": visits, "visits_per_s": visits / (t_walk * 1e-3),

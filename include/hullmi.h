@@ -107,7 +107,17 @@ enum hull_msc_mode { HULL_MSC_COUNT = 0, HULL_MSC_NEIGHBOR_DIFF = 1 };
 /* SM threshold. MAX_SLOPE follows Algorithm 3: M_t = M at the last voxel (in
  * linear order) whose slope max_{w in B(v)} M(v) - M(w) is largest; FRACTION
  * sets M_t by frac_den * M > frac_num * max M. H3 = {M > M_t} (Section 3.4). */
-enum hull_sm_mode { HULL_SM_FRACTION = 0, HULL_SM_MAX_SLOPE = 1 };
+enum hull_sm_mode { HULL_SM_FRACTION = 0, HULL_SM_MAX_SLOPE = 1, HULL_SM_EDGE = 2 };
+/* EDGE (scope SLICE only) follows the per-slice rule of Section 3.4's text:
+ * M_t is the largest M on the slice's strongest edge and H3 = {M >= M_t}. The
+ * paper's edge detector (a modified Canny) is not given; this one is, exactly
+ * in integers: Sobel gx, gy on the slice, G = |gx| + |gy| (0 on the slice
+ * border); direction (1,0) if 5|gy| <= 2|gx|, (0,1) if 5|gx| <= 2|gy|, else
+ * (1,1) when gx and gy share a sign and (1,-1) otherwise; p is an edge pixel
+ * iff G(p) > 0, G(p) > G(p - d) and G(p) >= G(p + d); the seed is the edge
+ * pixel of largest G (ties: largest index); the edge is the 8-connected set of
+ * edge pixels q with frac_den * G(q) >= frac_num * G(seed) that holds the
+ * seed; a slice without edge pixels keeps nothing. */
 /* statistic of the SM threshold over the whole volume or per z-slice */
 enum hull_scope { HULL_SCOPE_VOLUME = 0, HULL_SCOPE_SLICE = 1 };
 /* B(v) = {w : d(v, w) <= 1} (Section 3.3) in voxel units: v and its face

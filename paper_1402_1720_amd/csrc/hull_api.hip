@@ -101,8 +101,14 @@ void fill_u64(void *p, unsigned long long v, int64_t n, hipStream_t s)
     k_fill_u64<<<b, kBlock, 0, s>>>(reinterpret_cast<unsigned long long *>(p), v, n);
 }
 
-// Workspace of the SM rules: one 64-bit slot per z-slice (covers both scopes).
-size_t sm_ws_bytes(const hullmi_grid *g) { return align_up((size_t)g->nz * 8); }
+// Workspace of the SM rules: one 64-bit slot per z-slice (covers both scopes),
+// and for the EDGE rule a threshold per slice, the packed gradient per voxel
+// and the overflow space of the edge lists (two ints per voxel).
+size_t sm_ws_bytes(const hullmi_grid *g)
+{
+    const size_t V = (size_t)g->nx * g->ny * g->nz;
+    return 2 * align_up((size_t)g->nz * 8) + align_up(V * 8) + align_up(V * 8);
+}
 
 // Device properties the launch shapes depend on (queried per call: cheap).
 struct DevProps {
@@ -312,6 +318,25 @@ int run_sm_mask(const hullmi_grid *g, const int32_t *M, uint8_t *mask, int num, 
 {
     if (!mask) return HULL_OK;
     const int64_t V = voxels(g);
+    if (mode == HULL_SM_EDGE) {
+        char *b = reinterpret_cast<char *>(ws);
+        auto *seed = reinterpret_cast<unsigned long long *>(b);
+        auto *mt = reinterpret_cast<long long *>(b + align_up((size_t)g->nz * 8));
+        auto *gp = reinterpret_cast<unsigned long long *>(b + 2 * align_up((size_t)g->nz * 8));
+        auto *glist = reinterpret_cast<int *>(b + 2 * align_up((size_t)g->nz * 8) + align_up((size_t)V * 8));
+        const int64_t plane = (int64_t)g->nx * g->ny;
+        fill_u64(seed, 0ull, g->nz, s);
+        k_sm_edge_thin<<<dim3((unsigned)((plane + kBlock - 1) / kBlock), (unsigned)g->nz), kBlock, 0, s>>>(
+            M, gp, seed, g->nx, g->ny);
+        // edge lists in LDS up to all the LDS there is (two ints per entry)
+        const DevProps dp = dev_props();
+        const size_t lim = allow_max_lds(reinterpret_cast<const void *>(k_sm_edge_trace), dp.max_lds);
+        const int cap = (int)std::min<int64_t>((int64_t)(lim / 8), plane);
+        k_sm_edge_trace<<<(unsigned)g->nz, 1024, (size_t)cap * 8, s>>>(M, gp, seed, mt, glist, g->nx,
+                                                                       g->ny, num, den, cap);
+        k_sm_edge_mask<<<blocks_for(V), kBlock, 0, s>>>(M, mt, mask, V, plane);
+        return launch_status();
+    }
     const int64_t seg_len = scope == HULL_SCOPE_SLICE ? (int64_t)g->nx * g->ny : V;
     const int64_t nseg = V / seg_len;
     auto *seg = reinterpret_cast<unsigned long long *>(ws);
@@ -335,7 +360,9 @@ bool msc_args_ok(int n_t, int mode, int nbr)
 
 bool sm_args_ok(int num, int den, int mode, int scope, int nbr)
 {
-    return den > 0 && num >= 0 && (mode == HULL_SM_FRACTION || mode == HULL_SM_MAX_SLOPE) &&
+    if (mode == HULL_SM_EDGE && scope != HULL_SCOPE_SLICE) return false;
+    return den > 0 && num >= 0 &&
+           (mode == HULL_SM_FRACTION || mode == HULL_SM_MAX_SLOPE || mode == HULL_SM_EDGE) &&
            (scope == HULL_SCOPE_VOLUME || scope == HULL_SCOPE_SLICE) &&
            (nbr == HULL_NBR_INPLANE4 || nbr == HULL_NBR_SPATIAL6);
 }

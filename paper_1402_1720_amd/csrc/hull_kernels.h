@@ -83,6 +83,13 @@ __global__ void k_seg_slope_argmax(const int *M, unsigned long long *out, int nx
                                    int nbr, int64_t seg_len);
 __global__ void k_sm_mask(const int *M, uint8_t *mask, int64_t V, int64_t seg_len, int mode,
                           int num, int den, const unsigned long long *seg);
+__global__ void k_sm_edge_thin(const int *M, unsigned long long *gp, unsigned long long *seed, int nx,
+                               int ny);
+__global__ void k_sm_edge_trace(const int *M, const unsigned long long *gp,
+                                const unsigned long long *seed, long long *mt, int *glist, int nx,
+                                int ny, int num, int den, int cap);
+__global__ void k_sm_edge_mask(const int *M, const long long *mt, uint8_t *mask, int64_t V,
+                               int64_t plane);
 __global__ void k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt);
 constexpr int kFbpBinThreads = 1024;   // block of the LDS-binned FDK histogram
 __global__ void k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt,

@@ -537,4 +537,199 @@ k_fbp_backproject_tiles(const float *q, const float2 *cs, const int4 *fp, FbpDev
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// SM threshold from the strongest edge of each slice (the EDGE rule stated in
+// hullmi.h). Everything is integer: gradients, thinning, the edge component
+// and M_t are the same whatever the thread order.
+
+namespace {
+
+__device__ __forceinline__ bool sobel_at(const int *Ms, int nx, int ny, int i, int j,
+                                         long long &gx, long long &gy)
+{
+    if (i < 1 || j < 1 || i > nx - 2 || j > ny - 2) return false;
+    auto at = [&](int a, int b) { return (long long)Ms[(int64_t)b * nx + a]; };
+    gx = (at(i + 1, j - 1) + 2 * at(i + 1, j) + at(i + 1, j + 1)) -
+         (at(i - 1, j - 1) + 2 * at(i - 1, j) + at(i - 1, j + 1));
+    gy = (at(i - 1, j + 1) + 2 * at(i, j + 1) + at(i + 1, j + 1)) -
+         (at(i - 1, j - 1) + 2 * at(i, j - 1) + at(i + 1, j - 1));
+    return true;
+}
+
+__device__ __forceinline__ long long grad_l1(const int *Ms, int nx, int ny, int i, int j)
+{
+    long long gx, gy;
+    if (!sobel_at(Ms, nx, ny, i, j, gx, gy)) return 0;
+    return (gx < 0 ? -gx : gx) + (gy < 0 ? -gy : gy);
+}
+
+// index of q in the sorted list idx[0, n), or -1
+__device__ __forceinline__ int find_sorted(const int *idx, int n, int q)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (idx[mid] < q) lo = mid + 1; else hi = mid;
+    }
+    return lo < n && idx[lo] == q ? lo : -1;
+}
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v)
+{
+    __shared__ unsigned long long part[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_down(v, o, 64);
+        v = w > v ? w : v;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x + 63) / 64; ++i) v = part[i] > v ? part[i] : v;
+        part[0] = v;
+    }
+    __syncthreads();
+    const unsigned long long r = part[0];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace
+
+// Per pixel: the L1 gradient G and whether thinning keeps it, packed as
+// (G << 1) | edge; per slice the seed key (G << 22) | pixel of the strongest
+// edge pixel (ties to the larger pixel index), one atomic per block.
+__global__ void __launch_bounds__(256)
+k_sm_edge_thin(const int *M, unsigned long long *gp, unsigned long long *seed, int nx, int ny)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    const int k = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int *Ms = M + (int64_t)k * plane;
+    unsigned long long key = 0;
+    if (p < plane) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        long long gx = 0, gy = 0;
+        long long G = 0;
+        bool edge = false;
+        if (sobel_at(Ms, nx, ny, i, j, gx, gy)) {
+            const long long ax = gx < 0 ? -gx : gx, ay = gy < 0 ? -gy : gy;
+            G = ax + ay;
+            int di, dj;
+            if (5 * ay <= 2 * ax) { di = 1; dj = 0; }
+            else if (5 * ax <= 2 * ay) { di = 0; dj = 1; }
+            else if ((gx > 0) == (gy > 0)) { di = 1; dj = 1; }
+            else { di = 1; dj = -1; }
+            edge = G > 0 && G > grad_l1(Ms, nx, ny, i - di, j - dj) &&
+                   G >= grad_l1(Ms, nx, ny, i + di, j + dj);
+        }
+        gp[(int64_t)k * plane + p] = ((unsigned long long)G << 1) | (edge ? 1ull : 0ull);
+        if (edge) key = ((unsigned long long)G << 22) | (unsigned long long)p;
+    }
+    key = block_max_u64(key);
+    if (threadIdx.x == 0 && key) atomicMax(seed + k, key);
+}
+
+// One block per slice: the edge pixels eligible for the seed's edge
+// (den G >= num G(seed), and the seed itself) are listed in raster order;
+// min-label propagation with pointer jumping over their 8-neighbourhoods
+// labels the components; M_t = the largest M on the seed's component. The
+// list lives in LDS when it fits `cap` entries, else in `glist` (two arrays
+// of `plane` ints per slice).
+__global__ void __launch_bounds__(1024)
+k_sm_edge_trace(const int *M, const unsigned long long *gp, const unsigned long long *seed,
+                long long *mt, int *glist, int nx, int ny, int num, int den, int cap)
+{
+    extern __shared__ int lsh[];
+    __shared__ int wsum[16];
+    __shared__ int total, changed;
+    const int64_t plane = (int64_t)nx * ny;
+    const int k = blockIdx.x;
+    const unsigned long long key = seed[k];
+    if (key == 0) {
+        if (threadIdx.x == 0) mt[k] = -1;
+        return;   // uniform
+    }
+    const long long Gs = (long long)(key >> 22);
+    const int sp = (int)(key & ((1ull << 22) - 1));
+    const unsigned long long *g = gp + (int64_t)k * plane;
+    auto eligible = [&](int64_t p) {
+        const unsigned long long w = g[p];
+        return (w & 1ull) && ((long long)den * (long long)(w >> 1) >= (long long)num * Gs || p == sp);
+    };
+    // raster-order compaction: thread t owns pixels [t * per, (t + 1) * per)
+    const int nt = blockDim.x, t = threadIdx.x;
+    const int64_t per = (plane + nt - 1) / nt;
+    const int64_t p0 = min((int64_t)t * per, plane), p1 = min(p0 + per, plane);
+    int mine = 0;
+    for (int64_t p = p0; p < p1; ++p) mine += eligible(p);
+    // block exclusive scan of the per-thread counts
+    int incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if ((t & 63) >= o) incl += y;
+    }
+    if ((t & 63) == 63) wsum[t >> 6] = incl;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int w = 0; w < (nt + 63) / 64; ++w) { const int c = wsum[w]; wsum[w] = run; run += c; }
+        total = run;
+    }
+    __syncthreads();
+    const int L = total;
+    int *idx = L <= cap ? lsh : glist + (int64_t)k * 2 * plane;
+    int *lab = L <= cap ? lsh + cap : idx + plane;
+    int pos = wsum[t >> 6] + incl - mine;
+    for (int64_t p = p0; p < p1; ++p)
+        if (eligible(p)) { idx[pos] = (int)p; lab[pos] = pos; ++pos; }
+    __syncthreads();
+    // labels fall to the smallest list position of each component
+    for (;;) {
+        if (t == 0) changed = 0;
+        __syncthreads();
+        for (int e = t; e < L; e += nt) {
+            const int p = idx[e], i = p % nx, j = p / nx;
+            int l = lab[e];
+            for (int b = j - 1; b <= j + 1; ++b)
+                for (int a = i - 1; a <= i + 1; ++a) {
+                    if (a < 0 || a >= nx || b < 0 || b >= ny || (a == i && b == j)) continue;
+                    const int f = find_sorted(idx, L, b * nx + a);
+                    if (f >= 0) l = min(l, lab[f]);
+                }
+            if (l < lab[e]) { lab[e] = l; changed = 1; }
+        }
+        __syncthreads();
+        for (int e = t; e < L; e += nt) lab[e] = lab[lab[e]];
+        __syncthreads();
+        // every thread reads the flag before thread 0 clears it for the next round
+        const int again = changed;
+        __syncthreads();
+        if (!again) break;
+    }
+    // the seed is an edge pixel, so it is listed
+    const int s = find_sorted(idx, L, sp);
+    const int ls = s >= 0 ? lab[s] : -1;
+    unsigned long long best = 0;
+    const int *Ms = M + (int64_t)k * plane;
+    for (int e = t; e < L; e += nt)
+        if (lab[e] == ls) {
+            const unsigned long long v = (unsigned long long)(unsigned)Ms[idx[e]] + 1ull;
+            best = v > best ? v : best;
+        }
+    best = block_max_u64(best);
+    if (t == 0) mt[k] = (long long)best - 1;
+}
+
+__global__ void k_sm_edge_mask(const int *M, const long long *mt, uint8_t *mask, int64_t V,
+                               int64_t plane)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const long long t = mt[v / plane];
+    mask[v] = t >= 0 && (long long)M[v] >= t;
+}
+
 }  // namespace hullmi

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libhullmi.so")
 HULL_OK, HULL_EINVAL, HULL_ENOMEM, HULL_EDEVICE, HULL_EBUSY, HULL_ENOTSUP, HULL_ETIMEDOUT = range(7)
 HULL_ACCUMULATE = 1
 HULL_MSC_COUNT, HULL_MSC_NEIGHBOR_DIFF = 0, 1
-HULL_SM_FRACTION, HULL_SM_MAX_SLOPE = 0, 1
+HULL_SM_FRACTION, HULL_SM_MAX_SLOPE, HULL_SM_EDGE = 0, 1, 2
 HULL_SCOPE_VOLUME, HULL_SCOPE_SLICE = 0, 1
 HULL_NBR_INPLANE4, HULL_NBR_SPATIAL6 = 0, 1
 (HULL_OP_SC, HULL_OP_MSC, HULL_OP_SM, HULL_OP_ALL, HULL_OP_FBP, HULL_OP_COUNT_LINES,

@@ -262,3 +262,10 @@ def test_session_argument_checks():
     assert L.hull_session_read(None, None, None, None, None, None, None, 1) == H.HULL_EINVAL
     assert L.hull_session_reset(None) == H.HULL_EINVAL
     assert L.hull_session_destroy(None) == H.HULL_EINVAL
+
+
+def test_library_resolves_every_symbol_at_load():
+    """Loading with RTLD_NOW fails on any symbol the library uses but does not
+    define (a kernel declared in one namespace and defined in another links
+    into a shared library and only fails when called)."""
+    ctypes.CDLL(H.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
