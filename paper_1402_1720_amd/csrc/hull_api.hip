@@ -450,9 +450,14 @@ void fbp_reconstruct(const hullmi_grid *grid, const FbpDev &p, const FbpWs &w,
                      const unsigned long long *sum, const unsigned *cnt, double unit, float *image,
                      uint8_t *mask, hipStream_t s)
 {
-    const size_t lds = (size_t)(3 * p.nu - 1) * sizeof(double);
+    // the kernel table and one row per wavefront of the block (up to 98 KB
+    // for 2048 bins per row, above the default dynamic LDS limit)
+    const size_t lds = (size_t)(2 * p.nu - 1 + kFbpFilterRows * p.nu) * sizeof(double);
+    allow_max_lds(reinterpret_cast<const void *>(k_fbp_filter), dev_props().max_lds);
     fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
-    k_fbp_filter<<<(unsigned)(p.n_angles * p.nv), kBlock, lds, s>>>(sum, cnt, w.q, p, unit);
+    const int64_t rows = (int64_t)p.n_angles * p.nv;
+    k_fbp_filter<<<(unsigned)((rows + kFbpFilterRows - 1) / kFbpFilterRows), 64 * kFbpFilterRows, lds,
+                   s>>>(sum, cnt, w.q, p, unit);
     k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
     FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
                   grid->x0, grid->y0, grid->z0};

@@ -94,6 +94,7 @@ __global__ void k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum,
 constexpr int kFbpBinThreads = 1024;   // block of the LDS-binned FDK histogram
 __global__ void k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt,
                               int64_t chunk, int nplanes);
+constexpr int kFbpFilterRows = 4;   // detector rows per filter block
 __global__ void k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p,
                              double unit);
 __global__ void k_fbp_trig(float2 *cs, FbpDev p);

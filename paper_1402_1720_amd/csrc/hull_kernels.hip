@@ -312,38 +312,44 @@ k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *c
 // cosine pre-weight, then the
 // Shepp-Logan convolution along u (FP64 accumulation in the order j = 0 ..
 // nu - 1, rows taken as zero outside the detector).
-constexpr int kFilterOut = 4;
-__global__ void __launch_bounds__(256)
+constexpr int kFilterOut = 5;
+constexpr int kFilterRows = kFbpFilterRows;   // one detector row per wavefront
+__global__ void __launch_bounds__(64 * kFilterRows)
 k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p, double unit)
 {
     extern __shared__ double sh[];
     const int nu = p.nu;
-    double *row = sh;             // nu
-    double *ker = sh + nu;        // 2 nu - 1, ker[m + nu - 1] = h[m]
-    const int64_t r = blockIdx.x; // k * nv + iv
-    const int iv = (int)(r % p.nv);
+    const int64_t nrows = (int64_t)p.n_angles * p.nv;
+    double *ker = sh;                              // 2 nu - 1, ker[m + nu - 1] = h[m]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *row = sh + 2 * nu - 1 + wave * nu;     // this wavefront's row
+    const int64_t r = (int64_t)blockIdx.x * kFilterRows + wave;   // k * nv + iv
     const double D = p.src_dist, du = p.du;
-    const double vc = (double)p.v0 + ((double)iv + 0.5) * (double)p.dv;
     const double pi = 3.14159265358979323846;
-    for (int iu = threadIdx.x; iu < nu; iu += blockDim.x) {
-        const int64_t b = r * nu + iu;
-        const unsigned c = cnt[b];
-        const double mean = c ? (double)(long long)sum[b] * unit / (double)c : 0.0;
-        const double uc = (double)p.u0 + ((double)iu + 0.5) * du;
-        row[iu] = mean * D / sqrt(D * D + uc * uc + vc * vc);
-    }
     for (int m = threadIdx.x; m < 2 * nu - 1; m += blockDim.x) {
         const double n = (double)(m - (nu - 1));
         ker[m] = -2.0 / (pi * pi * du * du * (4.0 * n * n - 1.0));
     }
+    const int iv = (int)(r % p.nv);
+    if (r < nrows) {
+        const double vc = (double)p.v0 + ((double)iv + 0.5) * (double)p.dv;
+        for (int iu = lane; iu < nu; iu += 64) {
+            const int64_t b = r * nu + iu;
+            const unsigned c = cnt[b];
+            const double mean = c ? (double)(long long)sum[b] * unit / (double)c : 0.0;
+            const double uc = (double)p.u0 + ((double)iu + 0.5) * du;
+            row[iu] = mean * D / sqrt(D * D + uc * uc + vc * vc);
+        }
+    }
     __syncthreads();
+    if (r >= nrows) return;
     // padded output: [n_angles][nv + 4][nu + 4], two zero bins on every side
     const int64_t k = r / p.nv;
     float *qr = q + (k * (p.nv + 4) + (iv + 2)) * (int64_t)(nu + 4) + 2;
-    // kFilterOut consecutive outputs per thread: output iu + c needs
+    // kFilterOut consecutive outputs per lane: output iu + c needs
     // ker[iu + c + nu - 1 - j]; the window of kernel values slides down by one
     // per j, so each j costs one kernel load and one (broadcast) row load
-    for (int iu = threadIdx.x * kFilterOut; iu < nu; iu += blockDim.x * kFilterOut) {
+    for (int iu = lane * kFilterOut; iu < nu; iu += 64 * kFilterOut) {
         double acc[kFilterOut], win[kFilterOut];
         const int top = iu + nu - 1;   // ker index of output iu at j = 0
 #pragma unroll
