@@ -460,16 +460,22 @@ k_bsc_carve(BscWs w, FbpDev p, DevGrid g, int lwords)
     }
     for (int j = threadIdx.x; j < lwords; j += blockDim.x) win[j] = 0u;
     __syncthreads();
+    const int64_t plane = (int64_t)g.nx * g.ny;
     int a0, a1, a2, b0, b1, b2;
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        if (!bin_line(w, p, g, w.list[i], a0, a1, a2, b0, b1, b2)) continue;
-        if (!line_meets_grid(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz)) continue;
-        int z0, z1;
-        line_z_cover(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz, z0, z1);
-        atomicMin(&zlo, z0);
+    // a window that holds the whole volume starts at voxel 0; a smaller one
+    // starts at the lowest slice the block's lines can meet
+    if ((int64_t)lwords * 32 < plane * g.nz) {
+        for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            if (!bin_line(w, p, g, w.list[i], a0, a1, a2, b0, b1, b2)) continue;
+            if (!line_meets_grid(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz)) continue;
+            int z0, z1;
+            line_z_cover(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz, z0, z1);
+            atomicMin(&zlo, z0);
+        }
+    } else if (threadIdx.x == 0) {
+        zlo = 0;
     }
     __syncthreads();
-    const int64_t plane = (int64_t)g.nx * g.ny;
     const int64_t wbase = zlo == INT_MAX ? 0 : ((int64_t)zlo * plane) & ~int64_t(31);
     const int64_t wbits = (int64_t)lwords * 32;
     unsigned long long skipped = 0, visits = 0;
