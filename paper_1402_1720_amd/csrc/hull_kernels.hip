@@ -639,8 +639,8 @@ k_sm_edge_thin(const int *M, unsigned long long *gp, unsigned long long *seed, i
 
 // One block per slice: the edge pixels eligible for the seed's edge
 // (den G >= num G(seed), and the seed itself) are listed in raster order;
-// min-label propagation with pointer jumping over their 8-neighbourhoods
-// labels the components; M_t = the largest M on the seed's component. The
+// union-find over their 8-neighbourhoods labels the components; M_t = the
+// largest M on the seed's component. The
 // list lives in LDS when it fits `cap` entries, else in `glist` (two arrays
 // of `plane` ints per slice).
 __global__ void __launch_bounds__(1024)
@@ -649,7 +649,7 @@ k_sm_edge_trace(const int *M, const unsigned long long *gp, const unsigned long 
 {
     extern __shared__ int lsh[];
     __shared__ int wsum[16];
-    __shared__ int total, changed;
+    __shared__ int total;
     const int64_t plane = (int64_t)nx * ny;
     const int k = blockIdx.x;
     const unsigned long long key = seed[k];
@@ -664,57 +664,97 @@ k_sm_edge_trace(const int *M, const unsigned long long *gp, const unsigned long 
         const unsigned long long w = g[p];
         return (w & 1ull) && ((long long)den * (long long)(w >> 1) >= (long long)num * Gs || p == sp);
     };
-    // raster-order compaction: thread t owns pixels [t * per, (t + 1) * per)
+    // raster-order compaction in coalesced chunks: lane t of the block takes
+    // pixels c0 + 4t .. c0 + 4t + 3 of each chunk of 4 * blockDim pixels; a
+    // block scan of the per-lane counts places them in order
     const int nt = blockDim.x, t = threadIdx.x;
-    const int64_t per = (plane + nt - 1) / nt;
-    const int64_t p0 = min((int64_t)t * per, plane), p1 = min(p0 + per, plane);
+    const int64_t chunk = (int64_t)4 * nt;
+    // the list goes to LDS when the slice's eligible pixels fit, else to
+    // global memory: count them first (coalesced as well)
     int mine = 0;
-    for (int64_t p = p0; p < p1; ++p) mine += eligible(p);
-    // block exclusive scan of the per-thread counts
-    int incl = mine;
+    for (int64_t c0 = 0; c0 < plane; c0 += chunk)
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if ((t & 63) >= o) incl += y;
-    }
-    if ((t & 63) == 63) wsum[t >> 6] = incl;
+        for (int u = 0; u < 4; ++u) {
+            const int64_t p = c0 + 4 * t + u;
+            mine += p < plane && eligible(p);
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
+    if ((t & 63) == 0) wsum[t >> 6] = mine;
     __syncthreads();
     if (t == 0) {
         int run = 0;
-        for (int w = 0; w < (nt + 63) / 64; ++w) { const int c = wsum[w]; wsum[w] = run; run += c; }
+        for (int w = 0; w < (nt + 63) / 64; ++w) run += wsum[w];
         total = run;
     }
     __syncthreads();
     const int L = total;
     int *idx = L <= cap ? lsh : glist + (int64_t)k * 2 * plane;
     int *lab = L <= cap ? lsh + cap : idx + plane;
-    int pos = wsum[t >> 6] + incl - mine;
-    for (int64_t p = p0; p < p1; ++p)
-        if (eligible(p)) { idx[pos] = (int)p; lab[pos] = pos; ++pos; }
-    __syncthreads();
-    // labels fall to the smallest list position of each component
-    for (;;) {
-        if (t == 0) changed = 0;
-        __syncthreads();
-        for (int e = t; e < L; e += nt) {
-            const int p = idx[e], i = p % nx, j = p / nx;
-            int l = lab[e];
-            for (int b = j - 1; b <= j + 1; ++b)
-                for (int a = i - 1; a <= i + 1; ++a) {
-                    if (a < 0 || a >= nx || b < 0 || b >= ny || (a == i && b == j)) continue;
-                    const int f = find_sorted(idx, L, b * nx + a);
-                    if (f >= 0) l = min(l, lab[f]);
-                }
-            if (l < lab[e]) { lab[e] = l; changed = 1; }
+    int run = 0;   // entries written by earlier chunks (the same in every lane)
+    for (int64_t c0 = 0; c0 < plane; c0 += chunk) {
+        bool el[4];
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t p = c0 + 4 * t + u;
+            el[u] = p < plane && eligible(p);
+            cnt += el[u];
         }
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if ((t & 63) >= o) incl += y;
+        }
+        __syncthreads();   // wsum of the previous chunk has been read
+        if ((t & 63) == 63) wsum[t >> 6] = incl;
         __syncthreads();
-        for (int e = t; e < L; e += nt) lab[e] = lab[lab[e]];
-        __syncthreads();
-        // every thread reads the flag before thread 0 clears it for the next round
-        const int again = changed;
-        __syncthreads();
-        if (!again) break;
+        int before = run;
+        for (int w = 0; w < (t >> 6); ++w) before += wsum[w];
+        int pos = before + incl - cnt;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (el[u]) {
+                idx[pos] = (int)(c0 + 4 * t + u);
+                lab[pos] = pos;
+                ++pos;
+            }
+        for (int w = 0; w < (nt + 63) / 64; ++w) run += wsum[w];
     }
+    __syncthreads();
+    // components by union-find over the list: every entry is united with its
+    // listed neighbours that come earlier in raster order (each pair once);
+    // roots hook the larger position under the smaller with a compare-and-
+    // swap, so parents only decrease and every root walk ends; then each
+    // entry takes its root
+    volatile int *par = lab;
+    auto root = [&](int x) {
+        while (par[x] != x) x = par[x];
+        return x;
+    };
+    for (int e = t; e < L; e += nt) {
+        const int p = idx[e], i = p % nx, j = p / nx;
+        const int nb[4][2] = {{i - 1, j - 1}, {i, j - 1}, {i + 1, j - 1}, {i - 1, j}};
+#pragma unroll
+        for (int n4 = 0; n4 < 4; ++n4) {
+            const int a = nb[n4][0], b = nb[n4][1];
+            if (a < 0 || a >= nx || b < 0) continue;
+            const int f = find_sorted(idx, L, b * nx + a);
+            if (f < 0) continue;
+            int x = e, y = f;
+            for (;;) {
+                x = root(x);
+                y = root(y);
+                if (x == y) break;
+                if (x < y) { const int tmp = x; x = y; y = tmp; }
+                if (atomicCAS(lab + x, x, y) == x) break;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < L; e += nt) lab[e] = root(e);
+    __syncthreads();
     // the seed is an edge pixel, so it is listed
     const int s = find_sorted(idx, L, sp);
     const int ls = s >= 0 ? lab[s] : -1;
