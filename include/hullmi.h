@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define HULLMI_ABI_VERSION 1
+#define HULLMI_ABI_VERSION 2
 
 typedef enum hull_status {
     HULL_OK = 0,
@@ -286,12 +286,13 @@ int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n,
 int hull_quantize(const hullmi_histories *hist, const hullmi_grid *grid, int32_t *status,
                   int32_t *q_in, int32_t *q_out, void *stream);
 
-/* Device bytes that one request of `op` (HULL_OP_SC, _MSC, _SM, _ALL or _FBP)
- * occupies when the library holds everything itself, as the server does: the
- * eight input arrays (n values each), every output of the op (counts, masks,
- * FBP image), the stats block and the op's workspace, each piece 256-byte
- * aligned. fbp may be NULL unless op is HULL_OP_FBP. (size_t)-1 on invalid
- * arguments. Servers admit requests by this figure against their budget. */
+/* Device bytes that one request of `op` (HULL_OP_SC, _MSC, _SM, _ALL, _FBP,
+ * _FBP_CUT or _SC_BINNED) occupies when the library holds everything itself,
+ * as the server does: the eight input arrays (n values each), every output of
+ * the op (counts, masks, FBP image), the two counter blocks and the op's
+ * workspace, each piece 256-byte aligned. fbp may be NULL unless op is one of
+ * the three that bin on the detector. (size_t)-1 on invalid arguments.
+ * Servers admit requests by this figure against their budget. */
 size_t hull_footprint_bytes(int op, const hullmi_grid *grid, int64_t n,
                             const hullmi_fbp_params *fbp);
 
@@ -351,16 +352,22 @@ int hull_session_destroy(hullmi_session *s);
  * least loaded stream, each stream with a workspace of its own, and on the
  * first launch captures the whole fork/join into a HIP graph that later
  * launches replay. A job is one per-scan call with device pointers exactly
- * as hull_sc / hull_msc / hull_sm / hull_all / hull_fbp take them.
+ * as hull_sc / hull_msc / hull_sm / hull_all / hull_fbp / hull_fbp_cut /
+ * hull_sc_binned take them.
  * ---------------------------------------------------------------------- */
 
 /* One scan of a batch. op selects the call; only the fields that call reads
  * matter: SC reads params.wepl_low and writes N (+ sc_mask); MSC reads
  * params.wepl_low / msc_n_t / msc_mode / nbr and writes N (+ msc_mask); SM
  * reads params.wepl_high / sm_* / nbr and writes M (+ sm_mask); ALL is
- * hull_all; FBP reads fbp and writes image (+ fbp_mask). Pointers are device
- * pointers owned by the caller and must stay valid until the plan is
- * destroyed; their contents may change between launches. */
+ * hull_all; FBP reads fbp and writes image (+ fbp_mask); FBP_CUT is
+ * hull_fbp_cut with bsc.cut_sigmas and writes image (+ fbp_mask); SC_BINNED
+ * is hull_sc_binned with fbp as its bins and bsc as its parameters, and
+ * writes bsc_mask (required) and bsc_stats (may be NULL). stats belongs to
+ * the counting ops (SC, MSC, SM, ALL) and is ignored by the others. Pointers
+ * are device pointers owned by the caller and must stay valid until the plan
+ * is destroyed; their contents may change between launches. HULL_ACCUMULATE
+ * in flags applies to the counting ops only. */
 typedef struct hullmi_job {
     int32_t op;
     uint32_t flags;
@@ -373,6 +380,9 @@ typedef struct hullmi_job {
     float *image;
     uint8_t *fbp_mask;
     hullmi_stats *stats;
+    hullmi_bsc_params bsc;
+    uint8_t *bsc_mask;
+    hullmi_bsc_stats *bsc_stats;
 } hullmi_job;
 
 /* Launch choices of a plan. streams: concurrent internal streams (1..16);
@@ -435,6 +445,8 @@ typedef struct hullmi_request {
     uint8_t *sc_mask, *msc_mask, *sm_mask;
     float *image;
     uint8_t *fbp_mask;
+    hullmi_bsc_params bsc;
+    uint8_t *bsc_mask;
 } hullmi_request;
 
 /* Outcome of a request. Times are steady-clock nanoseconds of the host:
@@ -443,7 +455,8 @@ typedef struct hullmi_request {
  * worker's stream; compute_ms covers the call alone. */
 typedef struct hullmi_result {
     int32_t status;
-    hullmi_stats stats;
+    hullmi_stats stats;          /* counting ops; zero for the others */
+    hullmi_bsc_stats bsc_stats;  /* HULL_OP_SC_BINNED; zero for the others */
     int64_t t_arrive_ns, t_admit_ns, t_done_ns;
     float device_ms, h2d_ms, compute_ms, d2h_ms;
 } hullmi_result;

@@ -757,9 +757,19 @@ void zero_counts(int32_t *N, int32_t *M, hullmi_stats *stats, int64_t V, hipStre
     fill_u64(stats, 0ull, (int64_t)(sizeof(hullmi_stats) / 8), s);
 }
 
+namespace {
+
+// The ops whose call takes detector bins (the FDK parameters).
+bool bins_op(int op)
+{
+    return op == HULL_OP_FBP || op == HULL_OP_FBP_CUT || op == HULL_OP_SC_BINNED;
+}
+
+}  // namespace
+
 size_t job_ws_bytes(const hullmi_job &j)
 {
-    return ws_bytes_of(j.op, &j.grid, j.hist.n, j.op == HULL_OP_FBP ? &j.fbp : nullptr);
+    return ws_bytes_of(j.op, &j.grid, j.hist.n, bins_op(j.op) ? &j.fbp : nullptr);
 }
 
 int job_check(const hullmi_job &j)
@@ -785,6 +795,13 @@ int job_check(const hullmi_job &j)
         return HULL_OK;
     case HULL_OP_FBP:
         return j.image && fbp_ok(&j.fbp) ? HULL_OK : HULL_EINVAL;
+    case HULL_OP_FBP_CUT:
+        return j.image && fbp_ok(&j.fbp) && j.bsc.cut_sigmas >= 0 && j.bsc.cut_sigmas <= 64 &&
+                       j.hist.n <= INT32_MAX
+                   ? HULL_OK : HULL_EINVAL;
+    case HULL_OP_SC_BINNED:
+        return j.bsc_mask && fbp_ok(&j.fbp) && bsc_ok(&j.bsc) && j.hist.n <= INT32_MAX
+                   ? HULL_OK : HULL_EINVAL;
     default:
         return HULL_EINVAL;
     }
@@ -809,6 +826,12 @@ int job_run(const hullmi_job &j, void *ws, size_t ws_bytes, hipStream_t s, int w
                         j.stats, ws, ws_bytes, s, walk_blocks);
     case HULL_OP_FBP:
         return fbp_impl(&j.hist, &j.grid, &j.fbp, j.image, j.fbp_mask, ws, ws_bytes, s);
+    case HULL_OP_FBP_CUT:
+        return fbp_cut_impl(&j.hist, &j.grid, &j.fbp, j.bsc.cut_sigmas, j.image, j.fbp_mask, ws,
+                            ws_bytes, s);
+    case HULL_OP_SC_BINNED:
+        return bsc_impl(&j.hist, &j.grid, &j.fbp, &j.bsc, nullptr, nullptr, nullptr, j.bsc_mask,
+                        j.bsc_stats, ws, ws_bytes, s);
     default:
         return HULL_EINVAL;
     }
@@ -816,7 +839,9 @@ int job_run(const hullmi_job &j, void *ws, size_t ws_bytes, hipStream_t s, int w
 
 size_t footprint_bytes(int op, const hullmi_grid *grid, int64_t n, const hullmi_fbp_params *fbp)
 {
-    if (op < HULL_OP_SC || op > HULL_OP_FBP || n < 0 || n > INT32_MAX) return (size_t)-1;
+    if (op < HULL_OP_SC || op == HULL_OP_COUNT_LINES || op > HULL_OP_FBP_CUT || n < 0 ||
+        n > INT32_MAX)
+        return (size_t)-1;
     const size_t ws = ws_bytes_of(op, grid, n, fbp);
     if (ws == (size_t)-1) return ws;
     const size_t V = (size_t)voxels(grid);
@@ -826,9 +851,12 @@ size_t footprint_bytes(int op, const hullmi_grid *grid, int64_t n, const hullmi_
     case HULL_OP_MSC:
     case HULL_OP_SM: out = align_up(4 * V) + align_up(V); break;
     case HULL_OP_ALL: out = 2 * align_up(4 * V) + 3 * align_up(V); break;
-    case HULL_OP_FBP: out = align_up(4 * V) + align_up(V); break;
+    case HULL_OP_FBP:
+    case HULL_OP_FBP_CUT: out = align_up(4 * V) + align_up(V); break;
+    case HULL_OP_SC_BINNED: out = align_up(V); break;
     }
-    return 8 * align_up(4 * (size_t)n) + out + align_up(sizeof(hullmi_stats)) + align_up(ws);
+    return 8 * align_up(4 * (size_t)n) + out + align_up(sizeof(hullmi_stats)) +
+           align_up(sizeof(hullmi_bsc_stats)) + align_up(ws);
 }
 
 }  // namespace hullmi

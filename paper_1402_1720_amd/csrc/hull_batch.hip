@@ -40,13 +40,19 @@ constexpr int kMaxStreams = 16;
 
 // Relative cost of a job for the stream assignment: walk steps grow with the
 // histories times the in-plane extent; the epilogue and FDK backprojection
-// with the voxels.
+// with the voxels; the binned SC with its histories (three record passes)
+// and its carve lines (one per bin, each about the in-plane extent long).
 double job_cost(const hullmi_job &j)
 {
     const double n = (double)j.hist.n;
     const double V = (double)j.grid.nx * j.grid.ny * j.grid.nz;
-    if (j.op == HULL_OP_FBP) return n * 4.0 + V * (double)j.fbp.n_angles / 8.0;
-    return n * 0.5 * (j.grid.nx + j.grid.ny) + V;
+    const double bins = (double)j.fbp.nu * j.fbp.nv * j.fbp.n_angles;
+    switch (j.op) {
+    case HULL_OP_FBP: return n * 4.0 + V * (double)j.fbp.n_angles / 8.0;
+    case HULL_OP_FBP_CUT: return n * 16.0 + V * (double)j.fbp.n_angles / 8.0;
+    case HULL_OP_SC_BINNED: return n * 12.0 + bins * 0.5 * (j.grid.nx + j.grid.ny) / 4.0 + V;
+    default: return n * 0.5 * (j.grid.nx + j.grid.ny) + V;
+    }
 }
 
 void free_plan(hullmi_plan *p)

@@ -46,9 +46,10 @@ struct Ticket {
 struct Carve {
     const float *in[8];
     int32_t *N = nullptr, *M = nullptr;
-    uint8_t *sc = nullptr, *msc = nullptr, *sm = nullptr, *fmask = nullptr;
+    uint8_t *sc = nullptr, *msc = nullptr, *sm = nullptr, *fmask = nullptr, *bmask = nullptr;
     float *image = nullptr;
     hullmi_stats *stats = nullptr;
+    hullmi_bsc_stats *bstats = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
     size_t total = 0;
@@ -86,11 +87,16 @@ Carve carve(char *base, const hullmi_request &r, size_t ws_bytes)
         c.sm = reinterpret_cast<uint8_t *>(take(V));
         break;
     case HULL_OP_FBP:
+    case HULL_OP_FBP_CUT:
         c.image = reinterpret_cast<float *>(take(4 * V));
         c.fmask = reinterpret_cast<uint8_t *>(take(V));
         break;
+    case HULL_OP_SC_BINNED:
+        c.bmask = reinterpret_cast<uint8_t *>(take(V));
+        break;
     }
     c.stats = reinterpret_cast<hullmi_stats *>(take(sizeof(hullmi_stats)));
+    c.bstats = reinterpret_cast<hullmi_bsc_stats *>(take(sizeof(hullmi_bsc_stats)));
     c.ws = take(ws_bytes);
     c.ws_bytes = ws_bytes;
     c.total = off;
@@ -107,6 +113,7 @@ hullmi_job job_of(const hullmi_request &r)
     j.grid = r.grid;
     j.params = r.params;
     j.fbp = r.fbp;
+    j.bsc = r.bsc;
     return j;
 }
 
@@ -153,6 +160,7 @@ int hullmi_server::process(const hullmi_request &r, char *mem, hipStream_t s, hi
     j.hist.angle_deg = c.in[6]; j.hist.wepl = c.in[7];
     j.N = c.N; j.M = c.M; j.sc_mask = c.sc; j.msc_mask = c.msc; j.sm_mask = c.sm;
     j.image = c.image; j.fbp_mask = c.fmask; j.stats = c.stats;
+    j.bsc_mask = c.bmask; j.bsc_stats = c.bstats;
     const int rc = job_run(j, c.ws, c.ws_bytes, s, 0);
     if (rc != HULL_OK) {
         (void)hipStreamSynchronize(s);
@@ -170,7 +178,10 @@ int hullmi_server::process(const hullmi_request &r, char *mem, hipStream_t s, hi
     out(r.sm_mask, c.sm, V);
     out(r.image, c.image, 4 * V);
     out(r.fbp_mask, c.fmask, V);
-    if (r.op != HULL_OP_FBP) out(&res->stats, c.stats, sizeof(hullmi_stats));   // FDK keeps none
+    out(r.bsc_mask, c.bmask, V);
+    // each op fills one counter block, or none (the FDK hulls)
+    if (r.op <= HULL_OP_ALL) out(&res->stats, c.stats, sizeof(hullmi_stats));
+    if (r.op == HULL_OP_SC_BINNED) out(&res->bsc_stats, c.bstats, sizeof(hullmi_bsc_stats));
     ok = ok && hipEventRecord(ev[3], s) == hipSuccess;
     ok = hipStreamSynchronize(s) == hipSuccess && ok;
     if (!ok) return HULL_EDEVICE;
@@ -250,7 +261,7 @@ bool request_ok(const hullmi_request &r)
     static uint8_t u8;
     static float f32;
     j.N = j.M = &i32;
-    j.sc_mask = j.msc_mask = j.sm_mask = j.fbp_mask = &u8;
+    j.sc_mask = j.msc_mask = j.sm_mask = j.fbp_mask = j.bsc_mask = &u8;
     j.image = &f32;
     return job_check(j) == HULL_OK;
 }
@@ -296,8 +307,9 @@ int hull_server_submit(hullmi_server *srv, const hullmi_request *req, uint64_t *
 {
     if (!srv || !req || !ticket) return HULL_EINVAL;
     if (!request_ok(*req)) return HULL_EINVAL;
-    const size_t fp = footprint_bytes(req->op, &req->grid, req->hist.n,
-                                      req->op == HULL_OP_FBP ? &req->fbp : nullptr);
+    const bool bins = req->op == HULL_OP_FBP || req->op == HULL_OP_FBP_CUT ||
+                      req->op == HULL_OP_SC_BINNED;
+    const size_t fp = footprint_bytes(req->op, &req->grid, req->hist.n, bins ? &req->fbp : nullptr);
     if (fp == (size_t)-1) return HULL_EINVAL;
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stopping) return HULL_EBUSY;

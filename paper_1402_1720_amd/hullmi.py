@@ -25,6 +25,7 @@ HULL_NBR_INPLANE4, HULL_NBR_SPATIAL6 = 0, 1
 (HULL_OP_SC, HULL_OP_MSC, HULL_OP_SM, HULL_OP_ALL, HULL_OP_FBP, HULL_OP_COUNT_LINES,
  HULL_OP_SC_BINNED, HULL_OP_FBP_CUT) = range(8)
 
+ABI_VERSION = 2          # the struct layouts below
 FIELDS = ("x_in", "y_in", "z_in", "x_out", "y_out", "z_out", "angle_deg", "wepl")
 
 
@@ -75,7 +76,8 @@ _OUT_FIELDS = [("N", ctypes.c_void_p), ("M", ctypes.c_void_p), ("sc_mask", ctype
 class hullmi_job(ctypes.Structure):
     _fields_ = ([("op", ctypes.c_int32), ("flags", ctypes.c_uint32), ("hist", hullmi_histories),
                  ("grid", hullmi_grid), ("params", hullmi_params), ("fbp", hullmi_fbp_params)]
-                + _OUT_FIELDS + [("stats", ctypes.c_void_p)])
+                + _OUT_FIELDS + [("stats", ctypes.c_void_p), ("bsc", hullmi_bsc_params),
+                                 ("bsc_mask", ctypes.c_void_p), ("bsc_stats", ctypes.c_void_p)])
 
 
 class hullmi_tuning(ctypes.Structure):
@@ -85,11 +87,17 @@ class hullmi_tuning(ctypes.Structure):
 
 class hullmi_request(ctypes.Structure):
     _fields_ = ([("op", ctypes.c_int32), ("hist", hullmi_histories), ("grid", hullmi_grid),
-                 ("params", hullmi_params), ("fbp", hullmi_fbp_params)] + _OUT_FIELDS)
+                 ("params", hullmi_params), ("fbp", hullmi_fbp_params)] + _OUT_FIELDS
+                + [("bsc", hullmi_bsc_params), ("bsc_mask", ctypes.c_void_p)])
+
+
+class hullmi_bsc_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in BSC_STATS_FIELDS]
 
 
 class hullmi_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("stats", hullmi_stats),
+                ("bsc_stats", hullmi_bsc_stats),
                 ("t_arrive_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
                 ("t_done_ns", ctypes.c_int64), ("device_ms", ctypes.c_float),
                 ("h2d_ms", ctypes.c_float), ("compute_ms", ctypes.c_float),
@@ -155,6 +163,9 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = res
+        if L.hull_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.hull_abi_version()}, this binding "
+                              f"expects {ABI_VERSION}: rebuild it")
         _lib_handle = L
     return _lib_handle
 
@@ -454,24 +465,30 @@ def hull_footprint_bytes(op: int, grid, n: int, fbp: Optional[hullmi_fbp_params]
 _OP_OUTPUTS = {
     HULL_OP_SC: ("N", "sc_mask"), HULL_OP_MSC: ("N", "msc_mask"), HULL_OP_SM: ("M", "sm_mask"),
     HULL_OP_ALL: ("N", "M", "sc_mask", "msc_mask", "sm_mask"), HULL_OP_FBP: ("image", "fbp_mask"),
+    HULL_OP_FBP_CUT: ("image", "fbp_mask"), HULL_OP_SC_BINNED: ("bsc_mask",),
 }
 _OUT_DTYPES = {"N": torch.int32, "M": torch.int32, "sc_mask": torch.uint8,
                "msc_mask": torch.uint8, "sm_mask": torch.uint8, "image": torch.float32,
-               "fbp_mask": torch.uint8}
+               "fbp_mask": torch.uint8, "bsc_mask": torch.uint8}
 
 
 def make_job(op: int, hist: Histories, grid, params: Optional[hullmi_params] = None,
              fbp: Optional[hullmi_fbp_params] = None, flags: int = 0, stats=None,
-             **outputs) -> hullmi_job:
+             bsc: Optional[hullmi_bsc_params] = None, bsc_stats=None, **outputs) -> hullmi_job:
     """``hullmi_job`` for one scan; outputs are device tensors named as the
-    struct fields (N, M, sc_mask, msc_mask, sm_mask, image, fbp_mask)."""
+    struct fields (N, M, sc_mask, msc_mask, sm_mask, image, fbp_mask,
+    bsc_mask). ``bsc`` defaults to the paper's binned SC parameters;
+    ``bsc_stats`` is an int64[6] device tensor."""
     g = make_grid(grid)
     V = _voxels(g)
     j = hullmi_job()
     j.op, j.flags, j.hist, j.grid = int(op), int(flags), hist.c, g
     j.params = params if params is not None else make_params()
+    j.bsc = bsc if bsc is not None else make_bsc_params()
     if fbp is not None:
         j.fbp = fbp
+    bp = _dev_ptr(bsc_stats, torch.int64, 6, "bsc_stats", hist.device)
+    j.bsc_stats = bp.value if bp is not None else None
     for k, t in outputs.items():
         if k not in _OUT_DTYPES:
             raise ValueError(f"unknown output {k}")
@@ -543,7 +560,7 @@ class Server:
 
     def submit(self, op: int, hist: Dict[str, "np.ndarray"], grid,
                params: Optional[hullmi_params] = None, fbp: Optional[hullmi_fbp_params] = None,
-               **outputs) -> int:
+               bsc: Optional[hullmi_bsc_params] = None, **outputs) -> int:
         """Queues one request; outputs are host numpy arrays named as the
         struct fields. Returns the ticket."""
         import numpy as np
@@ -555,6 +572,7 @@ class Server:
         r.hist = hullmi_histories(*[_host_ptr(hist[k], np.float32, n, k) if n else None
                                     for k in FIELDS], n)
         r.params = params if params is not None else make_params()
+        r.bsc = bsc if bsc is not None else make_bsc_params()
         if fbp is not None:
             r.fbp = fbp
         np_types = {torch.int32: np.int32, torch.uint8: np.uint8, torch.float32: np.float32}
@@ -576,8 +594,10 @@ class Server:
             return None
         _check(rc, "hull_server_wait")
         self._keep.pop(int(ticket), None)
-        out = {k: getattr(res, k) for k, _ in hullmi_result._fields_ if k != "stats"}
+        out = {k: getattr(res, k) for k, _ in hullmi_result._fields_
+               if k not in ("stats", "bsc_stats")}
         out["stats"] = {k: getattr(res.stats, k) for k, _ in hullmi_stats._fields_}
+        out["bsc_stats"] = {k: getattr(res.bsc_stats, k) for k in BSC_STATS_FIELDS}
         return out
 
     def stats(self) -> Dict[str, int]:

@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_version_and_strerror():
-    assert H.hull_abi_version() == 1
+    assert H.hull_abi_version() == H.ABI_VERSION == 2
     assert H.hull_strerror(H.HULL_OK) == "ok"
     assert H.hull_strerror(H.HULL_EINVAL) == "invalid argument"
     assert H.hull_strerror(12345) == "unknown status"
@@ -134,16 +134,24 @@ def test_footprint_counts_inputs_outputs_and_workspace():
     for op, outs in ((H.HULL_OP_SC, [4 * V, V]), (H.HULL_OP_MSC, [4 * V, V]),
                      (H.HULL_OP_SM, [4 * V, V]), (H.HULL_OP_ALL, [4 * V, 4 * V, V, V, V])):
         ws = H.hull_workspace_bytes(op, g, n)
-        want = 8 * al(4 * n) + sum(al(b) for b in outs) + al(48) + al(ws)
+        # two counter blocks of 48 bytes: the counting ops' and the binned SC's
+        want = 8 * al(4 * n) + sum(al(b) for b in outs) + 2 * al(48) + al(ws)
         assert H.hull_footprint_bytes(op, g, n) == want, op
     f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
-    ws = H.hull_workspace_bytes(H.HULL_OP_FBP, g, n, f)
-    assert H.hull_footprint_bytes(H.HULL_OP_FBP, g, n, f) == \
-        8 * al(4 * n) + al(4 * V) + al(V) + al(48) + al(ws)
+    for op, outs in ((H.HULL_OP_FBP, [4 * V, V]), (H.HULL_OP_FBP_CUT, [4 * V, V]),
+                     (H.HULL_OP_SC_BINNED, [V])):
+        ws = H.hull_workspace_bytes(op, g, n, f)
+        want = 8 * al(4 * n) + sum(al(b) for b in outs) + 2 * al(48) + al(ws)
+        assert H.hull_footprint_bytes(op, g, n, f) == want, op
     for bad in ((H.HULL_OP_COUNT_LINES, g, n), (H.HULL_OP_SC, g, -1), (H.HULL_OP_SC, g, 2 ** 31),
-                (H.HULL_OP_SC, _grid(ny=0), n), (H.HULL_OP_FBP, g, n)):
+                (H.HULL_OP_SC, _grid(ny=0), n), (H.HULL_OP_FBP, g, n), (H.HULL_OP_FBP_CUT, g, n),
+                (H.HULL_OP_SC_BINNED, g, n), (8, g, n)):
         with pytest.raises(H.HullError):
             H.hull_footprint_bytes(*bad)
+
+
+def _bins(src=2000.0):
+    return H.hullmi_fbp_params(src, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
 
 
 def _job(**kw):
@@ -167,7 +175,16 @@ def test_batch_plan_rejects_bad_jobs_before_touching_the_device():
     assert L.hull_batch_plan(jobs, 2, None, None) == H.HULL_EINVAL
     bad = [_job(N=None), _job(op=9), _job(op=H.HULL_OP_SM), _job(grid=_grid(nx=0)),
            _job(hist=_hist(null="wepl")), _job(op=H.HULL_OP_MSC, params=H.make_params(msc_n_t=0)),
-           _job(op=H.HULL_OP_FBP, image=FAKE.value)]
+           _job(op=H.HULL_OP_FBP, image=FAKE.value),
+           # binned SC and FDK after cuts: bad bins, a missing output, bad parameters
+           _job(op=H.HULL_OP_SC_BINNED, fbp=_bins(), bsc=H.make_bsc_params()),
+           _job(op=H.HULL_OP_SC_BINNED, fbp=_bins(src=0.0), bsc_mask=FAKE.value,
+                bsc=H.make_bsc_params()),
+           _job(op=H.HULL_OP_SC_BINNED, fbp=_bins(), bsc_mask=FAKE.value,
+                bsc=H.make_bsc_params(window=4)),
+           _job(op=H.HULL_OP_FBP_CUT, fbp=_bins(), bsc=H.make_bsc_params()),
+           _job(op=H.HULL_OP_FBP_CUT, fbp=_bins(), image=FAKE.value,
+                bsc=H.make_bsc_params(cut_sigmas=65))]
     for b in bad:
         arr = (H.hullmi_job * 2)(_job(), b)
         assert L.hull_batch_plan(arr, 2, None, ctypes.byref(out)) == H.HULL_EINVAL

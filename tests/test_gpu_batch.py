@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
 
-def _scans(n_scans=6, h_lo=2e3, h_hi=3e5, seed=0x5EED0104):
+def _scans(n_scans=8, h_lo=2e3, h_hi=3e5, seed=0x5EED0104):
     specs = gen.batch_specs(n_scans=n_scans, h_lo=h_lo, h_hi=h_hi, seed=seed)
     return specs, [gen.generate(s) for s in specs]
 
@@ -31,7 +31,12 @@ _OPS = [
                                  nbr=H.HULL_NBR_SPATIAL6)),
     (H.HULL_OP_FBP, None),
     (H.HULL_OP_ALL, H.make_params(sm_scope=H.HULL_SCOPE_SLICE)),
+    (H.HULL_OP_SC_BINNED, None),
+    (H.HULL_OP_FBP_CUT, None),
 ]
+_BINS = (H.HULL_OP_FBP, H.HULL_OP_FBP_CUT, H.HULL_OP_SC_BINNED)    # ops that take detector bins
+_COUNTING = (H.HULL_OP_SC, H.HULL_OP_MSC, H.HULL_OP_SM, H.HULL_OP_ALL)
+_BSC = H.make_bsc_params(wepl_low=1.0, cut_sigmas=3, window=5, thr_num=2, thr_den=5)
 
 
 def _outputs(op, V):
@@ -42,7 +47,10 @@ def _outputs(op, V):
             H.HULL_OP_SM: lambda: dict(M=z32(), sm_mask=z8()),
             H.HULL_OP_ALL: lambda: dict(N=z32(), M=z32(), sc_mask=z8(), msc_mask=z8(), sm_mask=z8()),
             H.HULL_OP_FBP: lambda: dict(image=torch.zeros(V, dtype=torch.float32, device=DEV),
-                                        fbp_mask=z8())}[op]()
+                                        fbp_mask=z8()),
+            H.HULL_OP_FBP_CUT: lambda: dict(image=torch.zeros(V, dtype=torch.float32, device=DEV),
+                                            fbp_mask=z8()),
+            H.HULL_OP_SC_BINNED: lambda: dict(bsc_mask=z8())}[op]()
 
 
 def _alone(op, params, fbp, hist, grid, outs, stats):
@@ -59,8 +67,12 @@ def _alone(op, params, fbp, hist, grid, outs, stats):
     elif op == H.HULL_OP_ALL:
         H.hull_all(hist, grid, p, outs["N"], outs["M"], outs["sc_mask"], outs["msc_mask"],
                    outs["sm_mask"], stats=stats)
-    else:
+    elif op == H.HULL_OP_FBP:
         H.hull_fbp(hist, grid, fbp, outs["image"], outs["fbp_mask"])
+    elif op == H.HULL_OP_FBP_CUT:
+        H.hull_fbp_cut(hist, grid, fbp, _BSC.cut_sigmas, outs["image"], outs["fbp_mask"])
+    else:
+        H.hull_sc_binned(hist, grid, fbp, _BSC, outs["bsc_mask"], stats=stats)
 
 
 @pytest.fixture(scope="module")
@@ -72,7 +84,7 @@ def batch_case():
         op, params = _OPS[i % len(_OPS)]
         grid = H.make_grid(spec.grid)
         V = spec.grid.voxels
-        fbp = H.make_fbp_params(spec.fbp_geometry()) if op == H.HULL_OP_FBP else None
+        fbp = H.make_fbp_params(spec.fbp_geometry()) if op in _BINS else None
         hist = H.Histories.from_numpy(h, DEV)
         ref = _outputs(op, V)
         ref_stats = torch.zeros(6, dtype=torch.int64, device=DEV)
@@ -89,7 +101,9 @@ def _plan(case, tuning, flags=0):
         outs = _outputs(c["op"], c["V"])
         stats = torch.zeros(6, dtype=torch.int64, device=DEV)
         jobs.append(H.make_job(c["op"], c["hist"], c["grid"], c["params"], c["fbp"], flags=flags,
-                               stats=stats if c["op"] != H.HULL_OP_FBP else None, **outs))
+                               stats=stats if c["op"] in _COUNTING else None, bsc=_BSC,
+                               bsc_stats=stats if c["op"] == H.HULL_OP_SC_BINNED else None,
+                               **outs))
         keep.append((outs, stats))
     return H.BatchPlan(jobs, keep=keep + [c["hist"] for c in case], tuning=tuning), keep
 
@@ -100,7 +114,7 @@ def _same(case, keep, factor=1):
             got = outs[k]
             want = ref * factor if k in ("N", "M") else ref
             assert torch.equal(got, want), (c["op"], k, c["spec"].grid.n, c["spec"].n_hist)
-        if c["op"] != H.HULL_OP_FBP and factor == 1:
+        if c["op"] in _COUNTING + (H.HULL_OP_SC_BINNED,) and factor == 1:
             assert torch.equal(stats, c["ref_stats"]), c["op"]
 
 
@@ -116,6 +130,17 @@ def test_alone_results_match_the_oracle(batch_case):
     for k, want in (("N", N), ("M", M), ("sc_mask", sc), ("msc_mask", msc), ("sm_mask", sm)):
         assert np.array_equal(c["ref"][k].cpu().numpy(), want), k
     assert c["ref_stats"].cpu().tolist() == [st[k] for k in H.STATS_FIELDS]
+
+
+def test_alone_binned_sc_matches_the_oracle(batch_case):
+    c = next(c for c in batch_case if c["op"] == H.HULL_OP_SC_BINNED)
+    r = oracle.sc_binned(c["h"], oracle.grid_of(c["spec"].grid),
+                         oracle.fbp_params(c["spec"].fbp_geometry()),
+                         oracle.bsc_params(wepl_low=1.0, cut_sigmas=3, window=5, thr_num=2,
+                                           thr_den=5))
+    assert np.array_equal(c["ref"]["bsc_mask"].cpu().numpy(), r["mask"])
+    assert H.bsc_stats_dict(c["ref_stats"]) == r["stats"]
+    assert r["stats"]["n_bins_carved"] > 0
 
 
 @pytest.mark.parametrize("streams,graph", [(1, 0), (3, 0), (3, 1), (8, 1)])
@@ -137,7 +162,8 @@ def test_batch_equals_alone_over_replays(batch_case, streams, graph):
 
 
 def test_batch_accumulates_across_graph_replays(batch_case):
-    case = [c for c in batch_case if c["op"] != H.HULL_OP_FBP]
+    # the counting ops add up; the binned SC ignores the flag and rewrites
+    case = [c for c in batch_case if c["op"] in _COUNTING + (H.HULL_OP_SC_BINNED,)]
     plan, keep = _plan(case, H.hullmi_tuning(2, 1, 0), flags=H.HULL_ACCUMULATE)
     for outs, stats in keep:
         for v in outs.values():
@@ -146,10 +172,13 @@ def test_batch_accumulates_across_graph_replays(batch_case):
     for rep in range(1, 4):
         plan.launch()
         torch.cuda.synchronize()
-        for c, (outs, _) in zip(case, keep):
+        for c, (outs, stats) in zip(case, keep):
             for k in ("N", "M"):
                 if k in outs:
                     assert torch.equal(outs[k], c["ref"][k] * rep), (c["op"], k, rep)
+            if c["op"] == H.HULL_OP_SC_BINNED:
+                assert torch.equal(outs["bsc_mask"], c["ref"]["bsc_mask"]), rep
+                assert torch.equal(stats, c["ref_stats"]), rep
     plan.close()
 
 
@@ -181,7 +210,8 @@ def test_walk_grid_cap_changes_nothing(batch_case):
 _HOST_OUT = {H.HULL_OP_SC: ("N", "sc_mask"), H.HULL_OP_MSC: ("N", "msc_mask"),
              H.HULL_OP_SM: ("M", "sm_mask"),
              H.HULL_OP_ALL: ("N", "M", "sc_mask", "msc_mask", "sm_mask"),
-             H.HULL_OP_FBP: ("image", "fbp_mask")}
+             H.HULL_OP_FBP: ("image", "fbp_mask"), H.HULL_OP_FBP_CUT: ("image", "fbp_mask"),
+             H.HULL_OP_SC_BINNED: ("bsc_mask",)}
 _NP = {"N": np.int32, "M": np.int32, "image": np.float32}
 
 
@@ -189,7 +219,7 @@ def _submit_all(srv, case):
     tickets = []
     for c in case:
         outs = {k: np.full(c["V"], 3, dtype=_NP.get(k, np.uint8)) for k in _HOST_OUT[c["op"]]}
-        t = srv.submit(c["op"], c["h"], c["grid"], c["params"], c["fbp"], **outs)
+        t = srv.submit(c["op"], c["h"], c["grid"], c["params"], c["fbp"], bsc=_BSC, **outs)
         tickets.append((t, outs))
     return tickets
 
@@ -202,8 +232,15 @@ def _check_served(case, tickets, srv):
         assert r["device_ms"] + 1e-3 >= r["compute_ms"] >= 0.0
         for k, a in outs.items():
             assert np.array_equal(a, c["ref"][k].cpu().numpy()), (c["op"], k)
-        if c["op"] != H.HULL_OP_FBP:
+        zero = dict.fromkeys(H.BSC_STATS_FIELDS, 0)
+        if c["op"] in _COUNTING:
             assert [r["stats"][k] for k in H.STATS_FIELDS] == c["ref_stats"].cpu().tolist()
+            assert r["bsc_stats"] == zero
+        elif c["op"] == H.HULL_OP_SC_BINNED:
+            assert r["bsc_stats"] == H.bsc_stats_dict(c["ref_stats"])
+            assert all(v == 0 for v in r["stats"].values())
+        else:
+            assert r["bsc_stats"] == zero and all(v == 0 for v in r["stats"].values())
 
 
 def test_served_mix_equals_alone(batch_case):
