@@ -18,7 +18,7 @@ constexpr int kHistPerThread = 32;
 constexpr int kHistPerBlock = kBinThreads * kHistPerThread;
 constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic walk
 constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
-constexpr int kTileThreads = 512;       // workgroup of the LDS walk
+constexpr int kTileThreads = 1024;      // workgroup of the LDS walk
 constexpr int kMaxTileVoxels = 65536;   // 16-bit counters: 128 KB of LDS
 constexpr int kItemsPerRange = 32768;   // a range holds at most 2x this many items
 constexpr int kWorkPerItem = 16;        // fixed cost of an item in visit units (set-up)

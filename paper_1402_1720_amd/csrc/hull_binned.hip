@@ -41,6 +41,22 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
     return s;
 }
 
+// Column of block b in the per-block count rows: blocks ordered by b % 8,
+// then b / 8. Runs of one sub-bin that lie next to each other in the item
+// list then come from blocks 8 apart (8 x 8192 histories), so the 64 items of
+// a walk wave hold lines of several gantry angles instead of one; lines that
+// are not parallel spread their LDS adds over more banks. (With 8 XCDs and
+// round-robin dispatch the neighbours also ran on one XCD.) The order inside
+// a sub-bin changes no count.
+constexpr int kRunStride = 8;
+__device__ __forceinline__ int blk_col(int b, int nblk)
+{
+    const int x = b % kRunStride;
+    int before = 0;
+    for (int i = 0; i < x; ++i) before += (nblk - i + kRunStride - 1) / kRunStride;
+    return before + b / kRunStride;
+}
+
 // Number of entries of the non-decreasing array a[lo..hi) that are <= x.
 __device__ __forceinline__ int count_le(const uint32_t *a, int lo, int hi, uint32_t x)
 {
@@ -133,6 +149,10 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
             fetch_geo(h0 + hist_at(r + 1), g_next);
         if (r + 2 < kHistPerThread && hist_at(r + 2) < nb) w_next2 = h.wepl[h0 + hist_at(r + 2)];
         uint32_t meta = 0;
+        // every history's record and length word is written (zeros when
+        // unused), so that the block writes whole cache lines
+        int q[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t lp = 0;
         if (!isfinite(wv)) {
             ++nsk;
         } else {
@@ -142,7 +162,6 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                 const float xi = cf.xi, yi = cf.yi, zi = cf.zi;
                 const float xo = cf.xo, yo = cf.yo, zo = cf.zo;
                 const float a = cf.a;
-                int q[6];
                 int stg = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) &&
                            isfinite(yo) && isfinite(zo) && isfinite(a))
                               ? kGeoOk
@@ -179,27 +198,27 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                             meta |= kMetaOverflow;
                             atomicAdd(&lh[w.nsub - 2 + cls], 1u);
                         } else {
-                            uint32_t lp = 0;
                             for (int k = k0; k <= k1; ++k) {
                                 const int lc = length_class(q, g.nx, g.ny, g.nz, k, w.nl, w.lwidth);
                                 lp |= (uint32_t)lc << (4 * (k - k0));
                                 atomicAdd(&lh[(cls * w.nz + k) * w.nl + lc], 1u);
                             }
-                            w.lpack[j] = lp;
                         }
-                        int2 *rec = reinterpret_cast<int2 *>(w.q + 6 * j);
-                        rec[0] = make_int2(q[0], q[1]);
-                        rec[1] = make_int2(q[2], q[3]);
-                        rec[2] = make_int2(q[4], q[5]);
                     }
                 }
             }
         }
+        int2 *rec = reinterpret_cast<int2 *>(w.q + 6 * j);
+        rec[0] = make_int2(q[0], q[1]);
+        rec[1] = make_int2(q[2], q[3]);
+        rec[2] = make_int2(q[4], q[5]);
+        w.lpack[j] = lp;
         w.meta[j] = meta;
     }
     __syncthreads();
+    const int col = blk_col((int)blockIdx.x, w.nblk);
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
-        w.blk[(int64_t)b * w.nblk + blockIdx.x] = lh[b];
+        w.blk[(int64_t)b * w.nblk + col] = lh[b];
     if (st) {
         unsigned long long v;
         v = block_sum(nl, red);  if (threadIdx.x == 0) add_stats(st, 0, v);
@@ -342,8 +361,9 @@ __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
 __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w)
 {
     __shared__ uint32_t cur[kMaxSubBins];
+    const int col = blk_col((int)blockIdx.x, w.nblk);
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
-        cur[b] = w.sub_start[b] + w.blk[(int64_t)b * w.nblk + blockIdx.x];
+        cur[b] = w.sub_start[b] + w.blk[(int64_t)b * w.nblk + col];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kHistPerBlock + threadIdx.x;
     // the next history's meta word, length classes and endpoint record are
