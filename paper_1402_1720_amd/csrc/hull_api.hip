@@ -187,7 +187,8 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
         off += align_up(nbytes);
         return p;
     };
-    w.q = reinterpret_cast<int32_t *>(take((size_t)B * 24));
+    w.hrec = reinterpret_cast<uint4 *>(take((size_t)B * 16));
+    w.oq = reinterpret_cast<int32_t *>(take((size_t)B * 24));
     w.meta = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
     w.lpack = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
     w.blk = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.nblk * 4));
@@ -199,7 +200,7 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.range_piece = reinterpret_cast<uint32_t *>(take((size_t)(w.max_ranges + 1) * 4));
     w.wprefix = reinterpret_cast<unsigned long long *>(take((size_t)(w.nsub + 1) * 8));
     w.ctl = reinterpret_cast<int32_t *>(take((size_t)kCtlWords * 4));
-    w.rec = reinterpret_cast<int32_t *>(take((size_t)imax * 24));
+    w.item = reinterpret_cast<uint4 *>(take((size_t)imax * 16));
     w.partial = reinterpret_cast<uint32_t *>(
         take(tile_fits(g) ? (size_t)w.max_slots * w.tile_words * 4 : 0));
     if (bytes) *bytes = off;
@@ -292,7 +293,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         k_bin_plan<<<1, 1024, 0, s>>>(wb);
         k_bin_scatter<<<wb.nblk, kBinThreads, 0, s>>>(nb, wb);
         if (tile_ok) {
-            k_item_setup<<<dp.cus * 8, 256, 0, s>>>(wb, g->nx, g->ny);
+            k_item_setup<<<dp.cus * 8, 256, (size_t)(wb.ntiles + 1) * 4, s>>>(wb, g->nx, g->ny);
             k_walk_tiles<<<walk_grid, kTileThreads, tile_bytes, s>>>(wb, g->nx, g->ny);
             dim3 rg((unsigned)((wb.tile_words + 255) / 256), (unsigned)wb.ntiles);
             k_reduce_tiles<<<rg, 256, 0, s>>>(wb, plane, N, M, stats);

@@ -33,8 +33,13 @@ constexpr uint32_t kMetaHigh = 1u << 24;
 enum : int { kCtlRanges = 0, kCtlItems = 1, kCtlOverflowStart = 2, kCtlOverflowCount = 3,
              kCtlOverflowLow = 4, kCtlWords = 16 };
 
+// A line the tile walk takes has every endpoint coordinate in
+// [-kPackLimit, kPackLimit) (1/1024 voxel): its record packs into 16 bytes.
+constexpr int kPackLimit = 1 << 20;
+
 struct BinWs {
-    int32_t *q;             // [B][6] quantised endpoints of the batch (one 24-byte record each)
+    uint4 *hrec;            // [B] per history: the packed endpoints of a tile line, else zeros
+    int32_t *oq;            // [B][6] quantised endpoints of the lines the global walk takes
     uint32_t *meta;         // per history
     uint32_t *lpack;        // per history: 4-bit length class per slice
     uint32_t *blk;          // [nsub][nblk] counts, then offsets
@@ -46,8 +51,9 @@ struct BinWs {
     uint32_t *range_piece;  // [max_ranges] first final range of each coarse range
     unsigned long long *wprefix;  // [nsub + 1] work prefix of the sub-bins
     int32_t *ctl;           // kCtlWords
-    int32_t *rec;           // [B * kMaxSlicesPerLine][6] per item: the line's endpoints,
-                            // replaced by its slice-walk state (SliceState) for the tiles
+    uint4 *item;            // [B * kMaxSlicesPerLine] per item: a tile item's packed
+                            // endpoints, replaced by its packed slice-walk state; the
+                            // history of an overflow item
     uint32_t *partial;      // [max_slots][tile_words]
     int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
     int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;

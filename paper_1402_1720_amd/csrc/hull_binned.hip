@@ -6,8 +6,9 @@
 //   plan     : sub-bin starts, slice (tile) starts, ranges of equal estimated
 //              work over the sorted item list
 //   scatter  : (history, slice) items in sub-bin order, each a copy of the
-//              history's 24-byte endpoint record
-//   setup    : each tile item's endpoints replaced by its slice-walk state
+//              history's 16-byte packed endpoint record
+//   setup    : each tile item's endpoints replaced by its packed slice-walk
+//              state
 //   walk     : persistent workgroups; each range is cut at slice boundaries
 //              into segments, each accumulated in a 16-bit LDS copy of its
 //              slice and written to its own partial slot
@@ -74,6 +75,41 @@ __device__ __forceinline__ int count_le(const uint32_t *a, int lo, int hi, uint3
 __device__ __forceinline__ int slot_of(const BinWs &w, int nranges, uint32_t x)
 {
     return count_le(w.range_start, 1, nranges + 1, x) + count_le(w.tile_start, 1, w.ntiles, x);
+}
+
+// Endpoints of a tile line, every coordinate in [-kPackLimit, kPackLimit),
+// as six 21-bit two's-complement fields, three in each 64-bit half: one
+// 16-byte store per item in the scatter instead of three 8-byte ones.
+__device__ __forceinline__ uint4 pack_line(const int q[6])
+{
+    auto f = [](int v) { return (uint64_t)(uint32_t)v & 0x1fffffull; };
+    const uint64_t lo = f(q[0]) | f(q[1]) << 21 | f(q[2]) << 42;
+    const uint64_t hi = f(q[3]) | f(q[4]) << 21 | f(q[5]) << 42;
+    return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+}
+
+__device__ __forceinline__ void unpack_line(const uint4 r, int q[6])
+{
+    const uint64_t lo = (uint64_t)r.x | (uint64_t)r.y << 32;
+    const uint64_t hi = (uint64_t)r.z | (uint64_t)r.w << 32;
+    // the field's top bit to bit 63, then an arithmetic shift back
+    auto g = [](uint64_t h, int off) { return (int)((int64_t)(h << (43 - off)) >> 43); };
+    q[0] = g(lo, 0); q[1] = g(lo, 21); q[2] = g(lo, 42);
+    q[3] = g(hi, 0); q[4] = g(hi, 21); q[5] = g(hi, 42);
+}
+
+// Slice-walk state in 16 bytes: d; the first and the last voxel of the slice
+// part (16 bits each, a slice tile has at most 65536 voxels); |Dy| and |Dx|
+// (below 2^19 on a tile line), the signs of the x and y steps and a flag for a
+// slice the line does not meet.
+constexpr uint32_t kStateEmpty = 1u << 21;
+
+__device__ __forceinline__ uint4 pack_state(const SliceState &s)
+{
+    if (s.first < 0) return make_uint4(0u, 0u, kStateEmpty, 0u);
+    return make_uint4((uint32_t)s.d, (uint32_t)s.first | (uint32_t)s.last << 16,
+                      (uint32_t)s.ay | (uint32_t)(s.sx < 0) << 19 | (uint32_t)(s.sy < 0) << 20,
+                      (uint32_t)s.ax);
 }
 
 // Approximate number of voxels of the line inside slice k (FP32, only used to
@@ -151,7 +187,8 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
         uint32_t meta = 0;
         // every history's record and length word is written (zeros when
         // unused), so that the block writes whole cache lines
-        int q[6] = {0, 0, 0, 0, 0, 0};
+        int q[6];
+        uint4 rec = make_uint4(0u, 0u, 0u, 0u);
         uint32_t lp = 0;
         if (!isfinite(wv)) {
             ++nsk;
@@ -194,10 +231,17 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                         // needs |D| < 2^19 on x and y, else the global walk takes the line
                         const int64_t adx = (int64_t)q[3] - q[0], ady = (int64_t)q[4] - q[1];
                         const bool wide = max(adx < 0 ? -adx : adx, ady < 0 ? -ady : ady) >= (int64_t(1) << 19);
-                        if (!tile_ok || ns > kMaxSlicesPerLine || wide) {
+                        bool packs = true;
+                        for (int a = 0; a < 6; ++a) packs &= q[a] >= -kPackLimit && q[a] < kPackLimit;
+                        if (!tile_ok || ns > kMaxSlicesPerLine || wide || !packs) {
                             meta |= kMetaOverflow;
                             atomicAdd(&lh[w.nsub - 2 + cls], 1u);
+                            int2 *o = reinterpret_cast<int2 *>(w.oq + 6 * j);
+                            o[0] = make_int2(q[0], q[1]);
+                            o[1] = make_int2(q[2], q[3]);
+                            o[2] = make_int2(q[4], q[5]);
                         } else {
+                            rec = pack_line(q);
                             for (int k = k0; k <= k1; ++k) {
                                 const int lc = length_class(q, g.nx, g.ny, g.nz, k, w.nl, w.lwidth);
                                 lp |= (uint32_t)lc << (4 * (k - k0));
@@ -208,10 +252,7 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                 }
             }
         }
-        int2 *rec = reinterpret_cast<int2 *>(w.q + 6 * j);
-        rec[0] = make_int2(q[0], q[1]);
-        rec[1] = make_int2(q[2], q[3]);
-        rec[2] = make_int2(q[4], q[5]);
+        w.hrec[j] = rec;
         w.lpack[j] = lp;
         w.meta[j] = meta;
     }
@@ -366,18 +407,17 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
         cur[b] = w.sub_start[b] + w.blk[(int64_t)b * w.nblk + col];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kHistPerBlock + threadIdx.x;
-    // the next history's meta word, length classes and endpoint record are
+    // the next history's meta word, length classes and packed record are
     // loaded (independently of each other) while the current one is placed;
     // the record of an unclassified history is read but not used
-    struct Next { uint32_t m, lp; int2 a, b, c; };
+    struct Next { uint32_t m, lp; uint4 rec; };
     auto fetch = [&](int r, Next &x) {
         const int64_t j = base + (int64_t)r * kBinThreads;
         x.m = 0;
         if (r < kHistPerThread && j < nb) {
             x.m = w.meta[j];
             x.lp = w.lpack[j];
-            const int2 *src = reinterpret_cast<const int2 *>(w.q + 6 * j);
-            x.a = src[0]; x.b = src[1]; x.c = src[2];
+            x.rec = w.hrec[j];
         }
     };
     Next nxt;
@@ -389,17 +429,20 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
         const uint32_t m = cu.m;
         if (!(m & kMetaValid)) continue;
         const int cls = (m & kMetaHigh) ? 1 : 0;
-        auto put = [&](uint32_t p) {
-            int2 *dst = reinterpret_cast<int2 *>(w.rec + 6 * (size_t)p);
-            dst[0] = cu.a; dst[1] = cu.b; dst[2] = cu.c;
-        };
         if (m & kMetaOverflow) {
-            put(atomicAdd(&cur[w.nsub - 2 + cls], 1u));
+            // the overflow walk reads the full record by history
+            const uint32_t j = (uint32_t)(base + (int64_t)r * kBinThreads);
+            w.item[atomicAdd(&cur[w.nsub - 2 + cls], 1u)] = make_uint4(j, 0u, 0u, 0u);
         } else {
             const int k0 = (int)(m & 0xfffu), ns = (int)((m >> 12) & 0xfffu);
             for (int k = k0; k < k0 + ns; ++k) {
                 const int lc = (int)((cu.lp >> (4 * (k - k0))) & 0xfu);
-                put(atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u));
+                // two 8-byte stores: scattered 16-byte stores took twice as
+                // long here (188 vs 367 us for 1.1e7 items)
+                uint2 *dst = reinterpret_cast<uint2 *>(
+                    w.item + atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u));
+                dst[0] = make_uint2(cu.rec.x, cu.rec.y);
+                dst[1] = make_uint2(cu.rec.z, cu.rec.w);
             }
         }
     }
@@ -410,16 +453,17 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
 // walk's lanes only run the loop.
 __global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
 {
+    extern __shared__ uint32_t ts[];   // the slice tile starts
+    for (int t = threadIdx.x; t <= w.ntiles; t += blockDim.x) ts[t] = w.tile_start[t];
+    __syncthreads();
     const int n = w.ctl[kCtlItems];
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        const int t = count_le(w.tile_start, 0, w.ntiles, (uint32_t)p) - 1;   // slice tile of p
-        int2 *r = reinterpret_cast<int2 *>(w.rec + 6 * (size_t)p);
-        const int2 a = r[0], b = r[1], c = r[2];
+        const int t = count_le(ts, 0, w.ntiles, (uint32_t)p) - 1;   // slice tile of p
+        int q[6];
+        unpack_line(w.item[p], q);
         SliceState st;
-        slice_state(a.x, a.y, b.x, b.y, c.x, c.y, nx, ny, t % w.nz, st);
-        r[0] = make_int2(st.d, st.first);
-        r[1] = make_int2(st.last, st.incx);
-        r[2] = make_int2(st.incy, st.steps);
+        slice_state(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, t % w.nz, st);
+        w.item[p] = pack_state(st);
     }
 }
 
@@ -452,21 +496,20 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
             // flight while the current line is walked
             const uint32_t S = blockDim.x;
             uint32_t it = x + threadIdx.x;
-            int2 c0 = make_int2(0, 0), c1 = c0, c2 = c0;
-            if (it < y) {
-                const int2 *r = reinterpret_cast<const int2 *>(w.rec + 6 * (size_t)it);
-                c0 = r[0]; c1 = r[1]; c2 = r[2];
-            }
+            uint4 c = make_uint4(0u, 0u, kStateEmpty, 0u);
+            if (it < y) c = w.item[it];
             while (it < y) {
-                const int2 a0 = c0, a1 = c1, a2 = c2;
-                if (it + S < y) {
-                    const int2 *r = reinterpret_cast<const int2 *>(w.rec + 6 * (size_t)(it + S));
-                    c0 = r[0]; c1 = r[1]; c2 = r[2];
-                }
-                if (a0.y >= 0)   // a slice the line meets
-                    walk_slice_lds16(a0.x, (int32_t)tile_base + a0.y, (int32_t)tile_base + a1.x,
-                                     a1.y, a2.x, (int32_t)(int16_t)(a2.y & 0xffff), a2.y >> 16,
+                const uint4 a = c;
+                if (it + S < y) c = w.item[it + S];
+                if (!(a.z & kStateEmpty)) {   // a slice the line meets
+                    const int32_t incx = (int32_t)((a.z & 0x7ffffu) << 11);
+                    const int32_t incy = -(int32_t)(a.w << 11);
+                    const int32_t ox = (a.z >> 19) & 1u ? -2 : 2;
+                    const int32_t oy = (a.z >> 20) & 1u ? -2 * nx : 2 * nx;
+                    walk_slice_lds16((int32_t)a.x, (int32_t)(tile_base + 2 * (a.y & 0xffffu)),
+                                     (int32_t)(tile_base + 2 * (a.y >> 16)), incx, incy, ox, oy,
                                      nx + ny);
+                }
                 it += S;
             }
             // the loop's LDS adds are issued from inline assembly, which the
@@ -548,7 +591,7 @@ k_walk_overflow(BinWs w, int nx, int ny, int nz, int *N, int *M, hullmi_stats *s
     const int nlow = w.ctl[kCtlOverflowLow];
     unsigned long long vl = 0, vh = 0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        const int32_t *q = w.rec + 6 * (size_t)(start + t);
+        const int32_t *q = w.oq + 6 * (size_t)w.item[start + t].x;
         const bool high = t >= nlow;
         GlobalAcc3 acc{high ? M : N};
         const int v = walk_line(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, nz, acc);

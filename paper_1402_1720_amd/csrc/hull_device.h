@@ -48,14 +48,30 @@ __device__ __forceinline__ int quantize_point(float c, float s, float x, float y
     return kGeoOk;
 }
 
-// floor(a / b) for b > 0 when the quotient is known to satisfy |a / b| < 2^12:
-// an FP32 estimate (relative error a few 2^-24, so within 2^-10 of a / b) is
-// off by at most one after flooring, and two exact integer comparisons fix it.
-__device__ __forceinline__ int64_t floor_div_small(int64_t a, int64_t b)
+// Exact product of two int32 values. Every factor of the set-up below fits in
+// 32 bits: coordinates are below 2^26 in magnitude (2^27 after a slice
+// shift, grid axes at most 2048 voxels), so differences, entry distances and
+// next-crossing distances stay below 2^28 and every product below 2^56.
+__device__ __forceinline__ int64_t mul64(int32_t a, int32_t b) { return (int64_t)a * (int64_t)b; }
+
+// Voxel index on a moving axis at the entry key e / A of the entry axis:
+// floor(num / (kQ A)) with num = P A + D e, or ceil(num / (kQ A)) - 1 when
+// `up`; -1 when it lies outside [0, n). Once num is known to lie in range the
+// quotient is below n <= 2048, and its FP32 estimate (a few 2^-24 relative
+// error) is within 2^-10 of it: flooring is off by at most one, and two exact
+// comparisons fix that.
+__device__ __forceinline__ int entry_index(int32_t P, int32_t D, int32_t e, int32_t A, bool up, int n)
 {
-    int64_t q = (int64_t)floorf((float)a * __builtin_amdgcn_rcpf((float)b));
-    if (q * b > a) --q;
-    if ((q + 1) * b <= a) ++q;
+    const int64_t num = mul64(P, A) + mul64(D, e);
+    const int64_t lim = mul64(n * kQ, A);
+    if (up ? (num <= 0 || num > lim) : (num < 0 || num >= lim)) return -1;
+    // up: ceil(num / den) - 1 = floor((num - 1) / den) for integers
+    const int64_t a = up ? num - 1 : num;
+    const float est = (float)a * __builtin_amdgcn_rcpf((float)A) * (1.0f / (float)kQ);
+    int q = (int)floorf(est);
+    q = max(0, min(q, n - 1));
+    if (mul64(q * kQ, A) > a) --q;
+    if (mul64((q + 1) * kQ, A) <= a) ++q;
     return q;
 }
 
@@ -82,37 +98,35 @@ struct WalkInit {
 __device__ __forceinline__ bool walk_init(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
                                           int nx, int ny, int nz, WalkInit &w)
 {
-    const int64_t Px = qix, Py = qiy, Pz = qiz;
-    const int64_t Dx = (int64_t)qox - qix, Dy = (int64_t)qoy - qiy, Dz = (int64_t)qoz - qiz;
-    const int64_t Lx = (int64_t)kQ * nx, Ly = (int64_t)kQ * ny, Lz = (int64_t)kQ * nz;
-    // a fixed axis must already lie inside the grid
-    if (Dx == 0 && (Px < 0 || Px >= Lx)) return false;
-    if (Dy == 0 && (Py < 0 || Py >= Ly)) return false;
-    if (Dz == 0 && (Pz < 0 || Pz >= Lz)) return false;
-    const int64_t Ax = Dx < 0 ? -Dx : Dx, Ay = Dy < 0 ? -Dy : Dy, Az = Dz < 0 ? -Dz : Dz;
-    // entry key of each moving axis: t = en / A, sigma = (D < 0)
-    const int64_t enx = Dx > 0 ? -Px : Px - Lx;
-    const int64_t eny = Dy > 0 ? -Py : Py - Ly;
-    const int64_t enz = Dz > 0 ? -Pz : Pz - Lz;
-    const int gx = Dx < 0, gy = Dy < 0, gz = Dz < 0;
+    const int32_t P[3] = {qix, qiy, qiz};
+    const int32_t D[3] = {qox - qix, qoy - qiy, qoz - qiz};
+    const int n[3] = {nx, ny, nz};
+    int32_t A[3], en[3];
+    int g[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        // a fixed axis must already lie inside the grid
+        if (D[b] == 0 && (P[b] < 0 || P[b] >= kQ * n[b])) return false;
+        A[b] = D[b] < 0 ? -D[b] : D[b];
+        // entry key of a moving axis: t = en / A, sigma = (D < 0)
+        en[b] = D[b] > 0 ? -P[b] : P[b] - kQ * n[b];
+        g[b] = D[b] < 0;
+    }
     // the latest entry key decides where the line enters the grid
     int wa = -1;
-    int64_t ew = 0, aw = 1;
+    int32_t ew = 0, aw = 1;
     int gw = 0;
-    if (Ax) { wa = 0; ew = enx; aw = Ax; gw = gx; }
-    if (Ay) {
-        const int64_t l = eny * aw, r = ew * Ay;
-        if (wa < 0 || l > r || (l == r && gy > gw)) { wa = 1; ew = eny; aw = Ay; gw = gy; }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (!A[b]) continue;
+        if (wa >= 0) {
+            const int64_t l = mul64(en[b], aw), r = mul64(ew, A[b]);
+            if (!(l > r || (l == r && g[b] > gw))) continue;
+        }
+        wa = b; ew = en[b]; aw = A[b]; gw = g[b];
     }
-    if (Az) {
-        const int64_t l = enz * aw, r = ew * Az;
-        if (wa < 0 || l > r || (l == r && gz > gw)) { wa = 2; ew = enz; aw = Az; gw = gz; }
-    }
-    const int64_t den = (int64_t)kQ * aw;
     // voxel index of each axis at the entry key
-    int64_t c[3];
-    const int64_t P[3] = {Px, Py, Pz}, D[3] = {Dx, Dy, Dz};
-    const int n[3] = {nx, ny, nz};
+    int c[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         if (b == wa) {
@@ -120,26 +134,22 @@ __device__ __forceinline__ bool walk_init(int qix, int qiy, int qiz, int qox, in
         } else if (D[b] == 0) {
             c[b] = P[b] >> 10;
         } else {
-            // c = floor(num / den), or ceil(num / den) - 1 for a decreasing axis
-            // when a decreasing axis decides the entry; checked against [0, n)
-            // before dividing (den > 0), so the quotient is small
-            const int64_t num = P[b] * aw + D[b] * ew;
-            const bool up = gw && D[b] < 0;
-            if (up ? (num <= 0 || num > (int64_t)n[b] * den) : (num < 0 || num >= (int64_t)n[b] * den))
-                return false;
-            c[b] = up ? -floor_div_small(-num, den) - 1 : floor_div_small(num, den);
+            // a decreasing axis rounds up when a decreasing axis decides the entry
+            c[b] = entry_index(P[b], D[b], ew, aw, gw && D[b] < 0, n[b]);
+            if (c[b] < 0) return false;
         }
     }
-    // next crossing per axis
-    const int64_t ex = Dx > 0 ? (int64_t)kQ * (c[0] + 1) - Px : (Dx < 0 ? Px - (int64_t)kQ * c[0] : 1);
-    const int64_t ey = Dy > 0 ? (int64_t)kQ * (c[1] + 1) - Py : (Dy < 0 ? Py - (int64_t)kQ * c[1] : 1);
-    const int64_t ez = Dz > 0 ? (int64_t)kQ * (c[2] + 1) - Pz : (Dz < 0 ? Pz - (int64_t)kQ * c[2] : 1);
-    w.dxy = 2 * (ex * Ay - ey * Ax) + (gx - gy);
-    w.dxz = 2 * (ex * Az - ez * Ax) + (gx - gz);
-    w.dyz = 2 * (ey * Az - ez * Ay) + (gy - gz);
-    w.Ax = Ax; w.Ay = Ay; w.Az = Az;
-    w.cx = (int)c[0]; w.cy = (int)c[1]; w.cz = (int)c[2];
-    w.sx = Dx > 0 ? 1 : -1; w.sy = Dy > 0 ? 1 : -1; w.sz = Dz > 0 ? 1 : -1;
+    // next crossing per axis (|e| < 2^28)
+    int32_t e[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        e[b] = D[b] > 0 ? kQ * (c[b] + 1) - P[b] : (D[b] < 0 ? P[b] - kQ * c[b] : 1);
+    w.dxy = 2 * (mul64(e[0], A[1]) - mul64(e[1], A[0])) + (g[0] - g[1]);
+    w.dxz = 2 * (mul64(e[0], A[2]) - mul64(e[2], A[0])) + (g[0] - g[2]);
+    w.dyz = 2 * (mul64(e[1], A[2]) - mul64(e[2], A[1])) + (g[1] - g[2]);
+    w.Ax = A[0]; w.Ay = A[1]; w.Az = A[2];
+    w.cx = c[0]; w.cy = c[1]; w.cz = c[2];
+    w.sx = D[0] > 0 ? 1 : -1; w.sy = D[1] > 0 ? 1 : -1; w.sz = D[2] > 0 ? 1 : -1;
     return true;
 }
 
@@ -250,13 +260,12 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
 // Walk state of A_i inside z-slice k for walk_slice_lds16, set up once per
 // (line, slice) from two walk_init calls restricted to the slice (forward for
 // the first voxel and d, reversed for the last voxel): the decision
-// variable, the byte offsets 2 * voxel of the first and the last
-// voxel, the changes of d per x and per y step, and the byte steps per x step
-// (low 16 bits of `steps`, signed) and per y step (high 16 bits, signed).
-// first = last = -1 when the line does not meet the slice inside the grid.
-// Exact when |D| < 2^19 on x and y (the int32 condition of the loop).
+// variable, the first and the last voxel (in-plane index), |D| on x and y
+// (d changes by 2048 Ay per x step and by -2048 Ax per y step) and the step
+// directions. first = last = -1 when the line does not meet the slice inside
+// the grid. Exact when |D| < 2^19 on x and y (the int32 condition of the loop).
 struct SliceState {
-    int32_t d, first, last, incx, incy, steps;
+    int32_t d, first, last, ax, ay, sx, sy;
 };
 
 __device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
@@ -266,16 +275,16 @@ __device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, 
     WalkInit a, b;
     if (!walk_init(qix, qiy, qiz - zs, qox, qoy, qoz - zs, nx, ny, 1, a) ||
         !walk_init(qox, qoy, qoz - zs, qix, qiy, qiz - zs, nx, ny, 1, b)) {
-        s.d = 0; s.first = -1; s.last = -1; s.incx = 0; s.incy = 0; s.steps = 0;
+        s.d = 0; s.first = -1; s.last = -1; s.ax = 0; s.ay = 0; s.sx = 1; s.sy = 1;
         return;
     }
     s.d = (int32_t)a.dxy;
-    s.first = 2 * (a.cx + nx * a.cy);
-    s.last = 2 * (b.cx + nx * b.cy);
-    s.incx = (int32_t)(2048 * a.Ay);
-    s.incy = (int32_t)(-2048 * a.Ax);
-    const int32_t ox = 2 * a.sx, oy = 2 * a.sy * nx;
-    s.steps = (int32_t)(((uint32_t)oy << 16) | ((uint32_t)ox & 0xffffu));
+    s.first = a.cx + nx * a.cy;
+    s.last = b.cx + nx * b.cy;
+    s.ax = (int32_t)a.Ax;
+    s.ay = (int32_t)a.Ay;
+    s.sx = a.sx;
+    s.sy = a.sy;
 }
 
 // Whether A_i is not empty, exactly when walk_init returns true: the entry key
@@ -286,36 +295,35 @@ __device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, 
 __device__ __forceinline__ bool line_meets_grid(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
                                                 int nx, int ny, int nz)
 {
-    const int64_t P[3] = {qix, qiy, qiz};
-    const int64_t D[3] = {(int64_t)qox - qix, (int64_t)qoy - qiy, (int64_t)qoz - qiz};
+    const int32_t P[3] = {qix, qiy, qiz};
+    const int32_t D[3] = {qox - qix, qoy - qiy, qoz - qiz};
     const int n[3] = {nx, ny, nz};
     int wa = -1;
-    int64_t ew = 0, aw = 1;
+    int32_t ew = 0, aw = 1;
     int gw = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const int64_t L = (int64_t)kQ * n[b];
+        const int32_t L = kQ * n[b];
         if (D[b] == 0) {
             if (P[b] < 0 || P[b] >= L) return false;
             continue;
         }
-        const int64_t A = D[b] < 0 ? -D[b] : D[b];
-        const int64_t en = D[b] > 0 ? -P[b] : P[b] - L;
+        const int32_t A = D[b] < 0 ? -D[b] : D[b];
+        const int32_t en = D[b] > 0 ? -P[b] : P[b] - L;
         const int g = D[b] < 0;
         if (wa >= 0) {
-            const int64_t l = en * aw, r = ew * A;
+            const int64_t l = mul64(en, aw), r = mul64(ew, A);
             if (!(l > r || (l == r && g > gw))) continue;
         }
         wa = b; ew = en; aw = A; gw = g;
     }
-    const int64_t den = (int64_t)kQ * aw;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         if (b == wa || D[b] == 0) continue;
-        const int64_t num = P[b] * aw + D[b] * ew;
+        const int64_t num = mul64(P[b], aw) + mul64(D[b], ew);
+        const int64_t lim = mul64(kQ * n[b], aw);
         const bool up = gw && D[b] < 0;
-        if (up ? (num <= 0 || num > (int64_t)n[b] * den) : (num < 0 || num >= (int64_t)n[b] * den))
-            return false;
+        if (up ? (num <= 0 || num > lim) : (num < 0 || num >= lim)) return false;
     }
     return true;
 }

@@ -349,6 +349,28 @@ def test_grid_wider_than_a_tile():
     assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
 
 
+def test_long_rows_and_far_endpoints():
+    """A 2048-voxel row: lines with an endpoint 1024 voxels or more from the
+    grid origin do not pack into 16-byte records and take the global-atomic
+    walk; the others go through the LDS tiles. Same counts as the oracle."""
+    rng = np.random.default_rng(19)
+    g = gen.Grid((2048, 3, 2), (0.4, 1.0, 2.0))
+    n = 30_000
+    near = rng.random(n) < 0.5
+    c = np.where(near, rng.uniform(-405.0, -20.0, n), rng.uniform(-400.0, 400.0, n))
+    half = rng.uniform(0.5, 9.5, n)
+    h = dict(x_in=c - half, x_out=c + half,
+             y_in=rng.uniform(-2.0, 2.0, n), y_out=rng.uniform(-2.0, 2.0, n),
+             z_in=rng.uniform(-2.5, 2.5, n), z_out=rng.uniform(-2.5, 2.5, n),
+             angle_deg=np.zeros(n), wepl=rng.choice(np.array([0.5, 3.0, 9.0]), n))
+    h = {k: np.asarray(v, np.float32) for k, v in h.items()}
+    G = oracle.grid_of(g)
+    rN, rM, rst = oracle.counts(h, G)
+    gN, gM, gst = gpu_counts(h, g)
+    assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
+    assert rN[: 1000].sum() > 0 and rN[1100:2048].sum() > 0
+
+
 def test_two_internal_batches():
     """More than 2^24 histories run as several internal batches."""
     spec = gen.config_spec(1, n_hist=(1 << 24) + 4097)
