@@ -113,32 +113,18 @@ __device__ __forceinline__ uint4 pack_state(const SliceState &s)
 }
 
 // Approximate number of voxels of the line inside slice k (FP32, only used to
-// group lines of similar length), as a class in [0, nl).
-__device__ __forceinline__ int length_class(const int q[6], int nx, int ny, int nz, int k, int nl,
-                                            int lwidth)
+// group lines of similar length), as a class in [0, nl): the in-plane extent
+// of the part of the slab that lies in the slice.
+__device__ __forceinline__ int length_class(const LineSlab &b, float rdz, int k, int nl, float rlw)
 {
-    const float s = 1.0f / (float)kQ;
-    const float p[3] = {q[0] * s, q[1] * s, q[2] * s};
-    const float d[3] = {(q[3] - q[0]) * s, (q[4] - q[1]) * s, (q[5] - q[2]) * s};
-    const float n[3] = {(float)nx, (float)ny, (float)nz};
-    float tlo = -3.0e38f, thi = 3.0e38f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] != 0.0f) {
-            const float r = __builtin_amdgcn_rcpf(d[a]);
-            const float t0 = (0.0f - p[a]) * r, t1 = (n[a] - p[a]) * r;
-            tlo = fmaxf(tlo, fminf(t0, t1));
-            thi = fminf(thi, fmaxf(t0, t1));
-        }
-    }
-    if (d[2] != 0.0f) {
-        const float r = __builtin_amdgcn_rcpf(d[2]);
-        const float t0 = ((float)k - p[2]) * r, t1 = ((float)(k + 1) - p[2]) * r;
+    float tlo = b.tlo, thi = b.thi;
+    if (b.d[2] != 0.0f) {
+        const float t0 = ((float)k - b.p[2]) * rdz, t1 = ((float)(k + 1) - b.p[2]) * rdz;
         tlo = fmaxf(tlo, fminf(t0, t1));
         thi = fminf(thi, fmaxf(t0, t1));
     }
-    const float len = (fabsf(d[0]) + fabsf(d[1])) * fmaxf(thi - tlo, 0.0f) + 1.0f;
-    const float c = fminf(len * __builtin_amdgcn_rcpf((float)lwidth), (float)(nl - 1));
+    const float len = (fabsf(b.d[0]) + fabsf(b.d[1])) * fmaxf(thi - tlo, 0.0f) + 1.0f;
+    const float c = fminf(len * rlw, (float)(nl - 1));
     return c > 0.0f ? (int)c : 0;
 }
 
@@ -218,12 +204,18 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                 } else {
                     if (low) ++nl; else ++nh;
                     int k0, k1;
-                    // exact test for an empty A_i, then a slice range that covers A_i
-                    // (a slice the line does not meet gives an empty item)
-                    if (!line_meets_grid(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz)) {
+                    // whether A_i is empty (from the slab where it is clear, else
+                    // exactly), then a slice range that covers A_i (a slice the
+                    // line does not meet gives an empty item)
+                    LineSlab sb;
+                    line_slab(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz, sb);
+                    int meets = slab_meets(sb, q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz);
+                    if (meets < 0)
+                        meets = line_meets_grid(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz);
+                    if (!meets) {
                         ++nmi;
                     } else {
-                        line_z_cover(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz, k0, k1);
+                        slab_z_cover(sb, g.nz, k0, k1);
                         const int cls = low ? 0 : 1;
                         const int ns = k1 - k0 + 1;
                         meta = kMetaValid | (cls ? kMetaHigh : 0u) | ((uint32_t)ns << 12) | (uint32_t)k0;
@@ -242,8 +234,10 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                             o[2] = make_int2(q[4], q[5]);
                         } else {
                             rec = pack_line(q);
+                            const float rdz = sb.d[2] != 0.0f ? __builtin_amdgcn_rcpf(sb.d[2]) : 0.0f;
+                            const float rlw = __builtin_amdgcn_rcpf((float)w.lwidth);
                             for (int k = k0; k <= k1; ++k) {
-                                const int lc = length_class(q, g.nx, g.ny, g.nz, k, w.nl, w.lwidth);
+                                const int lc = length_class(sb, rdz, k, w.nl, rlw);
                                 lp |= (uint32_t)lc << (4 * (k - k0));
                                 atomicAdd(&lh[(cls * w.nz + k) * w.nl + lc], 1u);
                             }

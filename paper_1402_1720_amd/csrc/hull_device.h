@@ -394,33 +394,79 @@ __device__ __forceinline__ bool line_meets_grid(int qix, int qiy, int qiz, int q
 // the grid): the z extent of the line's part inside the grid box in FP32,
 // widened by far more than its rounding error. Slices it adds that the line
 // does not meet are found empty by the exact slice set-up.
+// The FP32 slab of a line against the grid box: p and d in voxel units, and
+// the entry and exit parameters tlo, thi of P(t) = p + t d over the moving
+// axes (an axis with D = 0 is left out: it bounds nothing). err bounds the
+// FP32 error of tlo and thi, with room to spare: per moving axis the error of
+// (c - p) / d is below (n + 2 |p|) / |d| 2^-21 (p, d and the two operations
+// each rounded once), and err is 16 times the largest such bound.
+struct LineSlab {
+    float p[3], d[3];
+    float tlo, thi, err;
+};
+
+__device__ __forceinline__ void line_slab(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                          int nx, int ny, int nz, LineSlab &b)
+{
+    const float s = 1.0f / (float)kQ;
+    b.p[0] = qix * s; b.p[1] = qiy * s; b.p[2] = qiz * s;
+    b.d[0] = (float)((int64_t)qox - qix) * s;
+    b.d[1] = (float)((int64_t)qoy - qiy) * s;
+    b.d[2] = (float)((int64_t)qoz - qiz) * s;
+    const float n[3] = {(float)nx, (float)ny, (float)nz};
+    float tlo = -3.0e38f, thi = 3.0e38f, e = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (b.d[a] != 0.0f) {
+            const float t0 = (0.0f - b.p[a]) / b.d[a], t1 = (n[a] - b.p[a]) / b.d[a];
+            tlo = fmaxf(tlo, fminf(t0, t1));
+            thi = fminf(thi, fmaxf(t0, t1));
+            e = fmaxf(e, (n[a] + 2.0f * fabsf(b.p[a])) / fabsf(b.d[a]));
+        }
+    }
+    b.tlo = tlo;
+    b.thi = thi;
+    b.err = e * (1.0f / 131072.0f);
+}
+
+// Whether A_i is not empty, decided from the slab where the margin is clear:
+// 1 when the line passes through the inside of the box (tlo < thi by more
+// than twice the error bound), 0 when it clearly misses it or a fixed axis
+// lies outside the grid (exact, in integers), -1 when only the exact test
+// (line_meets_grid) can tell: a line that touches an edge, a face or a corner.
+__device__ __forceinline__ int slab_meets(const LineSlab &b, int qix, int qiy, int qiz, int qox,
+                                          int qoy, int qoz, int nx, int ny, int nz)
+{
+    if (qox == qix && (qix < 0 || qix >= kQ * nx)) return 0;
+    if (qoy == qiy && (qiy < 0 || qiy >= kQ * ny)) return 0;
+    if (qoz == qiz && (qiz < 0 || qiz >= kQ * nz)) return 0;
+    if (b.tlo < b.thi - 2.0f * b.err) return 1;
+    if (b.tlo > b.thi + 2.0f * b.err) return 0;
+    return -1;
+}
+
+// A range of z-slices that holds every slice A_i meets, from the slab.
+__device__ __forceinline__ void slab_z_cover(const LineSlab &b, int nz, int &k0, int &k1)
+{
+    const float nzf = (float)nz;
+    float za = b.p[2], zb = b.p[2];
+    if (b.d[2] != 0.0f) {
+        za = b.p[2] + b.tlo * b.d[2];
+        zb = b.p[2] + b.thi * b.d[2];
+    }
+    const float lo = fminf(za, zb), hi = fmaxf(za, zb);
+    const float m = (fabsf(b.p[2]) + fabsf(lo) + fabsf(hi) + nzf) * (1.0f / 65536.0f) + 1.0f / 1024.0f;
+    k0 = (int)fmaxf(floorf(lo - m), 0.0f);
+    k1 = (int)fminf(floorf(hi + m), nzf - 1.0f);
+    if (k1 < k0) k1 = k0;   // cannot happen for a line that meets the grid
+}
+
 __device__ __forceinline__ void line_z_cover(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
                                              int nx, int ny, int nz, int &k0, int &k1)
 {
-    const float s = 1.0f / (float)kQ;
-    const float p[3] = {qix * s, qiy * s, qiz * s};
-    const float d[3] = {(float)((int64_t)qox - qix) * s, (float)((int64_t)qoy - qiy) * s,
-                        (float)((int64_t)qoz - qiz) * s};
-    const float n[3] = {(float)nx, (float)ny, (float)nz};
-    float tlo = -3.0e38f, thi = 3.0e38f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] != 0.0f) {
-            const float t0 = (0.0f - p[a]) / d[a], t1 = (n[a] - p[a]) / d[a];
-            tlo = fmaxf(tlo, fminf(t0, t1));
-            thi = fminf(thi, fmaxf(t0, t1));
-        }
-    }
-    float za = p[2], zb = p[2];
-    if (d[2] != 0.0f) {
-        za = p[2] + tlo * d[2];
-        zb = p[2] + thi * d[2];
-    }
-    const float lo = fminf(za, zb), hi = fmaxf(za, zb);
-    const float m = (fabsf(p[2]) + fabsf(lo) + fabsf(hi) + n[2]) * (1.0f / 65536.0f) + 1.0f / 1024.0f;
-    k0 = (int)fmaxf(floorf(lo - m), 0.0f);
-    k1 = (int)fminf(floorf(hi + m), n[2] - 1.0f);
-    if (k1 < k0) k1 = k0;   // cannot happen for a line that meets the grid
+    LineSlab b;
+    line_slab(qix, qiy, qiz, qox, qoy, qoz, nx, ny, nz, b);
+    slab_z_cover(b, nz, k0, k1);
 }
 
 }  // namespace hullmi
