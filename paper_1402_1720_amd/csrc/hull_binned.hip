@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
         int q[6];
         unpack_line(w.item[p], q);
         SliceState st;
-        slice_state(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, t % w.nz, st);
+        slice_state_tile(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, t % w.nz, st);
         w.item[p] = pack_state(st);
     }
 }

@@ -349,6 +349,100 @@ __device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, 
     s.sy = D[1] > 0 ? 1 : -1;
 }
 
+// slice_state for a tile line (every endpoint coordinate below 2^20 in
+// magnitude, |D| < 2^19 on x and y), in FP64: with the slice shift (at most
+// 2047 slices) every entry distance is below 2^22 and every |D| below 2^21,
+// so every product below is below 2^44 and every sum below 2^46, all exact in
+// a double; FP64 multiplies run at the FP32 rate, the 64-bit integer ones
+// they replace at a quarter of it. The results equal slice_state's.
+__device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_t D[3], int nx,
+                                                int ny, bool check_z, int &cx, int &cy,
+                                                int32_t *dxy)
+{
+    const int n[3] = {nx, ny, 1};
+    double A[3], en[3];
+    int g[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (D[b] == 0 && (P[b] < 0 || P[b] >= kQ * n[b])) return false;
+        A[b] = (double)(D[b] < 0 ? -D[b] : D[b]);
+        en[b] = (double)(D[b] > 0 ? -P[b] : P[b] - kQ * n[b]);
+        g[b] = D[b] < 0;
+    }
+    int wa = -1;
+    double ew = 0.0, aw = 1.0;
+    int gw = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (D[b] == 0) continue;
+        if (wa >= 0) {
+            const double l = en[b] * aw, r = ew * A[b];
+            if (!(l > r || (l == r && g[b] > gw))) continue;
+        }
+        wa = b; ew = en[b]; aw = A[b]; gw = g[b];
+    }
+    if (check_z && wa != 2 && D[2] != 0) {
+        const double num = (double)P[2] * aw + (double)D[2] * ew;
+        const double lim = (double)kQ * aw;
+        if (gw && D[2] < 0 ? (num <= 0.0 || num > lim) : (num < 0.0 || num >= lim)) return false;
+    }
+    const double den = (double)kQ * aw;
+    const double rden = __builtin_amdgcn_rcp(den);
+    int c[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        if (b == wa) {
+            c[b] = D[b] > 0 ? 0 : n[b] - 1;
+        } else if (D[b] == 0) {
+            c[b] = P[b] >> 10;
+        } else {
+            const double num = (double)P[b] * aw + (double)D[b] * ew;
+            const double lim = (double)n[b] * den;
+            const bool up = gw && D[b] < 0;
+            if (up ? (num <= 0.0 || num > lim) : (num < 0.0 || num >= lim)) return false;
+            // up: ceil(num / den) - 1 = floor((num - 1) / den); the estimate is
+            // off by at most one, fixed by two exact comparisons
+            const double a = up ? num - 1.0 : num;
+            int q = (int)floor(a * rden);
+            q = max(0, min(q, n[b] - 1));
+            if ((double)q * den > a) --q;
+            if ((double)(q + 1) * den <= a) ++q;
+            c[b] = q;
+        }
+    }
+    cx = c[0];
+    cy = c[1];
+    if (dxy) {
+        const int32_t ex = D[0] > 0 ? kQ * (c[0] + 1) - P[0] : (D[0] < 0 ? P[0] - kQ * c[0] : 1);
+        const int32_t ey = D[1] > 0 ? kQ * (c[1] + 1) - P[1] : (D[1] < 0 ? P[1] - kQ * c[1] : 1);
+        *dxy = (int32_t)(2.0 * ((double)ex * A[1] - (double)ey * A[0]) + (double)(g[0] - g[1]));
+    }
+    return true;
+}
+
+__device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
+                                                 int nx, int ny, int k, SliceState &s)
+{
+    const int zs = k * kQ;
+    const int32_t P[3] = {qix, qiy, qiz - zs}, Q[3] = {qox, qoy, qoz - zs};
+    const int32_t D[3] = {qox - qix, qoy - qiy, qoz - qiz};
+    const int32_t R[3] = {-D[0], -D[1], -D[2]};
+    int fx, fy, lx, ly;
+    int32_t d;
+    if (!slice_entry_f64(P, D, nx, ny, true, fx, fy, &d) ||
+        !slice_entry_f64(Q, R, nx, ny, false, lx, ly, nullptr)) {
+        s.d = 0; s.first = -1; s.last = -1; s.ax = 0; s.ay = 0; s.sx = 1; s.sy = 1;
+        return;
+    }
+    s.d = d;
+    s.first = fx + nx * fy;
+    s.last = lx + nx * ly;
+    s.ax = D[0] < 0 ? -D[0] : D[0];
+    s.ay = D[1] < 0 ? -D[1] : D[1];
+    s.sx = D[0] > 0 ? 1 : -1;
+    s.sy = D[1] > 0 ? 1 : -1;
+}
+
 // Whether A_i is not empty, exactly when walk_init returns true: the entry key
 // as walk_init picks it, then every axis only range-checked, which needs no
 // division (for den > 0, floor(num / den) lies in [0, n) iff
