@@ -451,10 +451,18 @@ __global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
     for (int t = threadIdx.x; t <= w.ntiles; t += blockDim.x) ts[t] = w.tile_start[t];
     __syncthreads();
     const int n = w.ctl[kCtlItems];
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        const int t = count_le(ts, 0, w.ntiles, (uint32_t)p) - 1;   // slice tile of p
+    const int stride = gridDim.x * blockDim.x;
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // a thread's items increase, so its slice tile only moves forward; the
+    // next item's record is in flight while the current one is set up
+    int t = p < n ? count_le(ts, 0, w.ntiles, (uint32_t)p) - 1 : 0;
+    uint4 nxt = p < n ? w.item[p] : make_uint4(0u, 0u, 0u, 0u);
+    for (; p < n; p += stride) {
+        const uint4 cur = nxt;
+        if (p + stride < n) nxt = w.item[p + stride];
+        while (ts[t + 1] <= (uint32_t)p) ++t;   // slice tile of p
         int q[6];
-        unpack_line(w.item[p], q);
+        unpack_line(cur, q);
         SliceState st;
         slice_state_tile(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, t % w.nz, st);
         w.item[p] = pack_state(st);
