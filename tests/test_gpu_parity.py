@@ -349,6 +349,33 @@ def test_grid_wider_than_a_tile():
     assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
 
 
+def test_lines_through_grid_corners_edges_and_faces():
+    """Lines through a corner, along an edge or within a face of the grid box
+    (and through inner voxel corners): the FP32 slab cannot decide these, so
+    the exact integer test does; counts, masks and the miss counter equal the
+    oracle's."""
+    rng = np.random.default_rng(23)
+    g = gen.Grid((16, 12, 6), (1.0, 1.0, 1.0))
+    half = np.array(g.half)
+    n = 40_000
+    # a point on a voxel corner lattice, at or near the box boundary
+    c = np.stack([rng.integers(-1, 2 * int(h) + 2, n) - h for h in half], axis=1)
+    on_face = rng.random((n, 3)) < 0.5
+    c = np.where(on_face, np.sign(rng.random((n, 3)) - 0.5) * half, c)
+    d = rng.integers(-20 * 1024, 20 * 1024, (n, 3)) / 1024.0
+    d[rng.random((n, 3)) < 0.2] = 0.0   # some axes fixed, exactly on a plane
+    d[np.all(d == 0.0, axis=1), 0] = 1.0
+    h = dict(x_in=c[:, 0] - d[:, 0], y_in=c[:, 1] - d[:, 1], z_in=c[:, 2] - d[:, 2],
+             x_out=c[:, 0] + d[:, 0], y_out=c[:, 1] + d[:, 1], z_out=c[:, 2] + d[:, 2],
+             angle_deg=np.zeros(n), wepl=rng.choice(np.array([0.5, 9.0]), n))
+    h = {k: np.asarray(v, np.float32) for k, v in h.items()}
+    G = oracle.grid_of(g)
+    rN, rM, rst = oracle.counts(h, G)
+    gN, gM, gst = gpu_counts(h, g)
+    assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
+    assert 0 < rst["n_missed_grid"] < rst["n_low"] + rst["n_high"]
+
+
 def test_long_rows_and_far_endpoints():
     """A 2048-voxel row: lines with an endpoint 1024 voxels or more from the
     grid origin do not pack into 16-byte records and take the global-atomic
