@@ -156,8 +156,12 @@ inline bool tile_fits(const hullmi_grid *g) { return plane_of(g) <= kMaxTileVoxe
 // that the sub-bin histogram of a block fits its LDS.
 inline int length_classes(const hullmi_grid *g) { return std::max(1, std::min(16, 2048 / g->nz)); }
 
-// Workgroups of the persistent walk (and the least number of ranges).
-constexpr int kMinRanges = 1024;
+// Workgroups of the persistent walk at most, and ranges per workgroup: the
+// ranges of equal estimated work are dealt out round-robin, and two per
+// workgroup even out the estimate's errors (one per workgroup left the walk
+// 18% longer; four cost more in extra tile flushes than they saved).
+constexpr int kMaxWalkGroups = 1024;
+constexpr int kRangesPerGroup = 2;
 
 // Layout of the slice-binned counting workspace for batches of up to
 // min(n, kBatch) histories. With base == nullptr only the size is computed.
@@ -173,11 +177,13 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.nsub = w.ntiles * w.nl + 2;
     w.nblk = (int)((B + kHistPerBlock - 1) / kHistPerBlock);
     w.tile_words = tile_fits(g) ? (int)((plane_of(g) + 1) / 2) : 1;
-    w.min_ranges = kMinRanges;
-    // ranges: P0 = max(min_ranges, ceil(I / 32768)) coarse ranges, each split
-    // into at most ceil(items / 32768) pieces: P <= 2 P0 + I / 32768
+    w.min_ranges = kMaxWalkGroups * kRangesPerGroup;
+    // ranges: P0 = max(min_ranges, ceil(I / kItemsPerRange)) coarse ranges,
+    // each split into at most ceil(items / kItemsPerRange) pieces:
+    // P <= 2 P0 + I / kItemsPerRange
     const int64_t imax = B * kMaxSlicesPerLine;
-    const int64_t p0 = std::max<int64_t>(kMinRanges, (imax + kItemsPerRange - 1) / kItemsPerRange);
+    const int64_t p0 = std::max<int64_t>(kMaxWalkGroups * kRangesPerGroup,
+                                         (imax + kItemsPerRange - 1) / kItemsPerRange);
     w.max_ranges = (int)(2 * p0 + (imax + kItemsPerRange - 1) / kItemsPerRange);
     w.max_slots = w.max_ranges + w.ntiles;
     char *b = reinterpret_cast<char *>(base);
@@ -278,7 +284,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
                                                          tile_bytes) == hipSuccess && occ > 0)
             per_cu = occ;
     }
-    int walk_grid = std::min(dp.cus * per_cu, kMinRanges);
+    int walk_grid = std::min(dp.cus * per_cu, kMaxWalkGroups);
     if (walk_blocks > 0) walk_grid = std::min(walk_grid, walk_blocks);
     const DevGrid dg = dev_grid(g);
     const int plane = (int)plane_of(g);
@@ -286,7 +292,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         const int64_t nb = std::min<int64_t>(w.B, h->n - h0);
         BinWs wb = w;
         wb.nblk = (int)((nb + kHistPerBlock - 1) / kHistPerBlock);
-        wb.min_ranges = walk_grid;   // one range per resident workgroup at least
+        wb.min_ranges = kRangesPerGroup * walk_grid;
         k_bin_classify<<<wb.nblk, kBinThreads, 0, s>>>(*h, h0, nb, dg, e_low, e_high, N != nullptr,
                                                        M != nullptr, tile_ok ? 1 : 0, wb, stats);
         k_bin_scan_blocks<<<wb.nsub, 256, 0, s>>>(wb);

@@ -20,7 +20,8 @@ constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic 
 constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
 constexpr int kTileThreads = 1024;      // workgroup of the LDS walk
 constexpr int kMaxTileVoxels = 65536;   // 16-bit counters: 128 KB of LDS
-constexpr int kItemsPerRange = 32768;   // a range holds at most 2x this many items
+constexpr int kItemsPerRange = 65535;   // a range holds at most this many items: each adds
+                                        // at most 1 to a voxel, so a 16-bit counter holds it
 constexpr int kWorkPerItem = 16;        // fixed cost of an item in visit units (set-up)
 constexpr int64_t kBatch = int64_t(1) << 24;   // histories per internal batch
 

@@ -333,7 +333,7 @@ __device__ __forceinline__ unsigned long long item_work(const BinWs &w, int sub)
 // Single block: sub-bin and slice starts, then the ranges: P0 = max(min_ranges,
 // ceil(I / kItemsPerRange)) ranges of equal estimated work, each split again
 // where it holds more than kItemsPerRange items, so that a range never adds
-// more than 2^15 to one 16-bit counter.
+// more than 65535 to one 16-bit counter (an item adds at most 1 to a voxel).
 __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
 {
     __shared__ unsigned long long shw[17];

@@ -204,6 +204,32 @@ def test_walk_grid_cap_changes_nothing(batch_case):
     plan.close()
 
 
+def test_range_counters_at_their_cap():
+    """5 x 65,535 copies of one line in one slice, walked by a single
+    workgroup: the plan makes five ranges of exactly 65,535 items, each
+    filling the same 16-bit LDS counters to their largest value; the sums are
+    exact."""
+    g = gen.Grid((24, 20, 4), (1.0, 1.0, 2.5))
+    n = 5 * 65_535
+    one = dict(x_in=-30.0, y_in=-4.3, z_in=1.1, x_out=30.0, y_out=5.7, z_out=1.4, angle_deg=0.0)
+    h = {k: np.full(n, v, np.float32) for k, v in one.items()}
+    h["wepl"] = np.full(n, 0.5, np.float32)
+    rN, rM, rst = oracle.counts(h, oracle.grid_of(g))
+    assert rN.max() == n
+    hist = H.Histories.from_numpy(h, DEV)
+    V = g.voxels
+    N = torch.zeros(V, dtype=torch.int32, device=DEV)
+    M = torch.zeros(V, dtype=torch.int32, device=DEV)
+    st = torch.zeros(6, dtype=torch.int64, device=DEV)
+    job = H.make_job(H.HULL_OP_ALL, hist, g, H.make_params(), stats=st, N=N, M=M)
+    plan = H.BatchPlan([job], keep=[hist, N, M, st], tuning=H.hullmi_tuning(1, 0, 1))
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(N.cpu().numpy(), rN) and np.array_equal(M.cpu().numpy(), rM)
+    assert H.stats_dict(st) == rst
+    plan.close()
+
+
 # ---------------------------------------------------------------------------
 # serving
 
