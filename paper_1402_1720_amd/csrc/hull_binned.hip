@@ -555,14 +555,29 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N
         }
         slots[threadIdx.x] = sl;
         const int n = __syncthreads_count(in);
-        if (wd < w.tile_words)
-            for (int s = 0; s < n; ++s) {
+        if (wd < w.tile_words) {
+            // eight slots' words in flight at a time
+            auto word = [&](int s) {
                 const uint32_t q = slots[s];
-                if (q == 0xffffffffu) continue;
-                const uint32_t v = w.partial[(int64_t)q * w.tile_words + wd];
+                return q == 0xffffffffu ? 0u : w.partial[(int64_t)q * w.tile_words + wd];
+            };
+            int s = 0;
+            for (; s + 8 <= n; s += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = word(s + u);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    lo += v[u] & 0xffffu;
+                    hi += v[u] >> 16;
+                }
+            }
+            for (; s < n; ++s) {
+                const uint32_t v = word(s);
                 lo += v & 0xffffu;
                 hi += v >> 16;
             }
+        }
         if (n < 256) break;   // uniform: n is the same in every thread
         __syncthreads();      // slots are rewritten in the next round
     }
