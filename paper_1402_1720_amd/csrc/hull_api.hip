@@ -459,7 +459,7 @@ void fbp_reconstruct(const hullmi_grid *grid, const FbpDev &p, const FbpWs &w,
 {
     // the kernel table and one row per wavefront of the block (up to 98 KB
     // for 2048 bins per row, above the default dynamic LDS limit)
-    const size_t lds = (size_t)(2 * p.nu - 1 + kFbpFilterRows * p.nu) * sizeof(double);
+    const size_t lds = (size_t)(2 * p.nu + kFbpFilterRows * p.nu) * sizeof(double);
     allow_max_lds(reinterpret_cast<const void *>(k_fbp_filter), dev_props().max_lds);
     fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
     const int64_t rows = (int64_t)p.n_angles * p.nv;

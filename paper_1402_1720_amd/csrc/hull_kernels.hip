@@ -320,12 +320,15 @@ k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDe
     extern __shared__ double sh[];
     const int nu = p.nu;
     const int64_t nrows = (int64_t)p.n_angles * p.nv;
-    double *ker = sh;                              // 2 nu - 1, ker[m + nu - 1] = h[m]
+    // ker[m + nu - 1] = h[m] for |m| < nu, with one zero before it (ker[-1]),
+    // so that the sliding window below needs no bounds test
+    double *ker = sh + 1;                          // 2 nu - 1 values after the zero
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *row = sh + 2 * nu - 1 + wave * nu;     // this wavefront's row
+    double *row = sh + 2 * nu + wave * nu;         // this wavefront's row
     const int64_t r = (int64_t)blockIdx.x * kFilterRows + wave;   // k * nv + iv
     const double D = p.src_dist, du = p.du;
     const double pi = 3.14159265358979323846;
+    if (threadIdx.x == 0) ker[-1] = 0.0;
     for (int m = threadIdx.x; m < 2 * nu - 1; m += blockDim.x) {
         const double n = (double)(m - (nu - 1));
         ker[m] = -2.0 / (pi * pi * du * du * (4.0 * n * n - 1.0));
@@ -361,10 +364,10 @@ k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDe
         for (int j = 0; j < nu; ++j) {
             const double x = row[j];
 #pragma unroll
-            for (int c = 0; c < kFilterOut; ++c) acc[c] += win[c] * x;
+            for (int c = 0; c < kFilterOut; ++c) acc[c] = __builtin_fma(win[c], x, acc[c]);
 #pragma unroll
             for (int c = kFilterOut - 1; c > 0; --c) win[c] = win[c - 1];
-            win[0] = top - j - 1 >= 0 ? ker[top - j - 1] : 0.0;
+            win[0] = ker[top - j - 1];   // index >= -1 (top >= nu - 1, j < nu)
         }
 #pragma unroll
         for (int c = 0; c < kFilterOut; ++c)
