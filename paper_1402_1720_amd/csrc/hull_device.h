@@ -381,8 +381,9 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
         }
         wa = b; ew = en[b]; aw = A[b]; gw = g[b];
     }
+    // products and sums below are exact in a double, so an FMA gives the same values
     if (check_z && wa != 2 && D[2] != 0) {
-        const double num = (double)P[2] * aw + (double)D[2] * ew;
+        const double num = __builtin_fma((double)P[2], aw, (double)D[2] * ew);
         const double lim = (double)kQ * aw;
         if (gw && D[2] < 0 ? (num <= 0.0 || num > lim) : (num < 0.0 || num >= lim)) return false;
     }
@@ -396,7 +397,7 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
         } else if (D[b] == 0) {
             c[b] = P[b] >> 10;
         } else {
-            const double num = (double)P[b] * aw + (double)D[b] * ew;
+            const double num = __builtin_fma((double)P[b], aw, (double)D[b] * ew);
             const double lim = (double)n[b] * den;
             const bool up = gw && D[b] < 0;
             if (up ? (num <= 0.0 || num > lim) : (num < 0.0 || num >= lim)) return false;
@@ -415,7 +416,8 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
     if (dxy) {
         const int32_t ex = D[0] > 0 ? kQ * (c[0] + 1) - P[0] : (D[0] < 0 ? P[0] - kQ * c[0] : 1);
         const int32_t ey = D[1] > 0 ? kQ * (c[1] + 1) - P[1] : (D[1] < 0 ? P[1] - kQ * c[1] : 1);
-        *dxy = (int32_t)(2.0 * ((double)ex * A[1] - (double)ey * A[0]) + (double)(g[0] - g[1]));
+        *dxy = (int32_t)(2.0 * __builtin_fma((double)ex, A[1], -((double)ey * A[0])) +
+                         (double)(g[0] - g[1]));
     }
     return true;
 }
@@ -515,7 +517,8 @@ __device__ __forceinline__ void line_slab(int qix, int qiy, int qiz, int qox, in
             const float t0 = (0.0f - b.p[a]) / b.d[a], t1 = (n[a] - b.p[a]) / b.d[a];
             tlo = fmaxf(tlo, fminf(t0, t1));
             thi = fminf(thi, fmaxf(t0, t1));
-            e = fmaxf(e, (n[a] + 2.0f * fabsf(b.p[a])) / fabsf(b.d[a]));
+            // a bound with room to spare: a reciprocal a few ulp off is fine
+            e = fmaxf(e, (n[a] + 2.0f * fabsf(b.p[a])) * __builtin_amdgcn_rcpf(fabsf(b.d[a])));
         }
     }
     b.tlo = tlo;
