@@ -101,16 +101,40 @@ __device__ __forceinline__ int carve_slice(int a0, int a1, int a2, int b0, int b
                                            int64_t wbits, unsigned *gbits)
 {
     const int zs = k * kQ;
-    WalkInit f, r;
-    if (!walk_init(a0, a1, a2 - zs, b0, b1, b2 - zs, nx, ny, 1, f) ||
-        !walk_init(b0, b1, b2 - zs, a0, a1, a2 - zs, nx, ny, 1, r))
-        return 0;
-    int off = f.cx + nx * f.cy;
-    const int last = r.cx + nx * r.cy;
-    const int64_t incx = 2048 * f.Ay, incy = -2048 * f.Ax;
-    const int ox = f.sx, oy = f.sy * nx;
+    int off, last;
+    int64_t d, incx, incy;
+    int ox, oy;
+    const int lim = 1 << 23;
+    if (max(max(abs(a0), abs(a1)), max(abs(a2), max(abs(b0), max(abs(b1), abs(b2))))) < lim) {
+        // exact in FP64 (the same result as the integer set-up below)
+        const int32_t P[3] = {a0, a1, a2 - zs}, Q[3] = {b0, b1, b2 - zs};
+        const int32_t D[3] = {b0 - a0, b1 - a1, b2 - a2}, R[3] = {a0 - b0, a1 - b1, a2 - b2};
+        int fx, fy, lx, ly;
+        double dd;
+        if (!slice_entry_f64(P, D, nx, ny, true, fx, fy, &dd) ||
+            !slice_entry_f64(Q, R, nx, ny, false, lx, ly, nullptr))
+            return 0;
+        off = fx + nx * fy;
+        last = lx + nx * ly;
+        d = (int64_t)dd;
+        incx = 2048 * (int64_t)abs(D[1]);
+        incy = -2048 * (int64_t)abs(D[0]);
+        ox = D[0] > 0 ? 1 : -1;
+        oy = (D[1] > 0 ? 1 : -1) * nx;
+    } else {
+        WalkInit f, r;
+        if (!walk_init(a0, a1, a2 - zs, b0, b1, b2 - zs, nx, ny, 1, f) ||
+            !walk_init(b0, b1, b2 - zs, a0, a1, a2 - zs, nx, ny, 1, r))
+            return 0;
+        off = f.cx + nx * f.cy;
+        last = r.cx + nx * r.cy;
+        incx = 2048 * f.Ay;
+        incy = -2048 * f.Ax;
+        ox = f.sx;
+        oy = f.sy * nx;
+        d = f.dxy;
+    }
     const int64_t sl = (int64_t)k * nx * ny;
-    int64_t d = f.dxy;
     int cnt = 0;
     for (int it = nx + ny; it > 0; --it) {
         const int64_t gi = sl + off, rel = gi - wbase;
@@ -486,9 +510,15 @@ k_bsc_carve(BscWs w, FbpDev p, DevGrid g, int lwords)
             ++skipped;
             continue;
         }
-        if (!line_meets_grid(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz)) continue;
+        // whether A is empty (from the slab where it is clear, else exactly),
+        // then the slices that cover it
+        LineSlab sb;
+        line_slab(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz, sb);
+        int meets = slab_meets(sb, a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz);
+        if (meets < 0) meets = line_meets_grid(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz);
+        if (!meets) continue;
         int z0, z1;
-        line_z_cover(a0, a1, a2, b0, b1, b2, g.nx, g.ny, g.nz, z0, z1);
+        slab_z_cover(sb, g.nz, z0, z1);
         for (int z = z0; z <= z1; ++z)
             visits += (unsigned long long)carve_slice(a0, a1, a2, b0, b1, b2, g.nx, g.ny, z, win,
                                                       wbase, wbits, w.cbits);

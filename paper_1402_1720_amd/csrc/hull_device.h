@@ -349,15 +349,16 @@ __device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, 
     s.sy = D[1] > 0 ? 1 : -1;
 }
 
-// slice_state for a tile line (every endpoint coordinate below 2^20 in
-// magnitude, |D| < 2^19 on x and y), in FP64: with the slice shift (at most
-// 2047 slices) every entry distance is below 2^22 and every |D| below 2^21,
-// so every product below is below 2^44 and every sum below 2^46, all exact in
-// a double; FP64 multiplies run at the FP32 rate, the 64-bit integer ones
-// they replace at a quarter of it. The results equal slice_state's.
+// The slice set-up in FP64. For endpoint coordinates below 2^23 in magnitude
+// (2^24 after the slice shift of at most 2047 slices) every entry distance is
+// below 2^25 and every |D| below 2^24, so every product below is below 2^49
+// and every sum below 2^51: all exact in a double, and the results equal
+// those of the integer set-up. FP64 multiplies run at the FP32 rate, the
+// 64-bit integer ones they replace at a quarter of it. A tile line (all
+// coordinates below 2^20, |D| < 2^19 on x and y) is well inside this range.
 __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_t D[3], int nx,
                                                 int ny, bool check_z, int &cx, int &cy,
-                                                int32_t *dxy)
+                                                double *dxy)
 {
     const int n[3] = {nx, ny, 1};
     double A[3], en[3];
@@ -416,8 +417,7 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
     if (dxy) {
         const int32_t ex = D[0] > 0 ? kQ * (c[0] + 1) - P[0] : (D[0] < 0 ? P[0] - kQ * c[0] : 1);
         const int32_t ey = D[1] > 0 ? kQ * (c[1] + 1) - P[1] : (D[1] < 0 ? P[1] - kQ * c[1] : 1);
-        *dxy = (int32_t)(2.0 * __builtin_fma((double)ex, A[1], -((double)ey * A[0])) +
-                         (double)(g[0] - g[1]));
+        *dxy = 2.0 * __builtin_fma((double)ex, A[1], -((double)ey * A[0])) + (double)(g[0] - g[1]);
     }
     return true;
 }
@@ -430,13 +430,13 @@ __device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int 
     const int32_t D[3] = {qox - qix, qoy - qiy, qoz - qiz};
     const int32_t R[3] = {-D[0], -D[1], -D[2]};
     int fx, fy, lx, ly;
-    int32_t d;
+    double d;
     if (!slice_entry_f64(P, D, nx, ny, true, fx, fy, &d) ||
         !slice_entry_f64(Q, R, nx, ny, false, lx, ly, nullptr)) {
         s.d = 0; s.first = -1; s.last = -1; s.ax = 0; s.ay = 0; s.sx = 1; s.sy = 1;
         return;
     }
-    s.d = d;
+    s.d = (int32_t)d;   // below 2^31 in magnitude on a tile line
     s.first = fx + nx * fy;
     s.last = lx + nx * ly;
     s.ax = D[0] < 0 ? -D[0] : D[0];
