@@ -42,9 +42,14 @@ __device__ __forceinline__ bool fbp_locate_vals(float xi, float yi, float zi, fl
     const float fv = (v - p.v0) * p.rdv;
     if (!(fabsf(fa) < 1.0e9f)) return false;
     if (!(fu >= 0.0f && fu < (float)p.nu && fv >= 0.0f && fv < (float)p.nv)) return false;
-    long long kk = (long long)rintf(fa) % p.n_angles;
-    if (kk < 0) kk += p.n_angles;
-    k = (int)kk;
+    // |fa| < 1e9 < 2^31: the angle index fits 32 bits, and it is almost always
+    // already in [0, n_angles), where no remainder is needed
+    int kk = (int)rintf(fa);
+    if ((unsigned)kk >= (unsigned)p.n_angles) {
+        kk %= p.n_angles;
+        if (kk < 0) kk += p.n_angles;
+    }
+    k = kk;
     iu = (int)floorf(fu);
     iv = (int)floorf(fv);
     fx = llrint((double)w * 65536.0);
