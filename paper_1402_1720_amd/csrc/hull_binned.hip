@@ -503,14 +503,20 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
             while (it < y) {
                 const uint4 a = c;
                 if (it + S < y) c = w.item[it + S];
-                if (!(a.z & kStateEmpty)) {   // a slice the line meets
-                    const int32_t incx = (int32_t)((a.z & 0x7ffffu) << 11);
-                    const int32_t incy = -(int32_t)(a.w << 11);
-                    const int32_t ox = (a.z >> 19) & 1u ? -2 : 2;
-                    const int32_t oy = (a.z >> 20) & 1u ? -2 * nx : 2 * nx;
-                    walk_slice_lds16((int32_t)a.x, (int32_t)(tile_base + 2 * (a.y & 0xffffu)),
-                                     (int32_t)(tile_base + 2 * (a.y >> 16)), incx, incy, ox, oy,
-                                     nx + ny);
+                const bool live = !(a.z & kStateEmpty);   // a slice the line meets
+                const int32_t incx = (int32_t)((a.z & 0x7ffffu) << 11);
+                const int32_t incy = -(int32_t)(a.w << 11);
+                const int32_t ox = (a.z >> 19) & 1u ? -2 : 2;
+                const int32_t oy = (a.z >> 20) & 1u ? -2 * nx : 2 * nx;
+                const int32_t off = (int32_t)(tile_base + 2 * (a.y & 0xffffu));
+                const int32_t last = (int32_t)(tile_base + 2 * (a.y >> 16));
+                // lines of one wave mostly share their step directions: when
+                // every live lane's d is odd (no corner can be hit), the wave
+                // takes the shorter loop
+                if (__all(!live || (a.x & 1u))) {
+                    if (live) walk_slice_lds16_odd((int32_t)a.x, off, last, incx, incy, ox, oy, nx + ny);
+                } else if (live) {
+                    walk_slice_lds16((int32_t)a.x, off, last, incx, incy, ox, oy, nx + ny);
                 }
                 it += S;
             }

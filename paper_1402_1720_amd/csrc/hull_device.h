@@ -257,6 +257,45 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
         : "vcc", "scc", "memory");
 }
 
+// walk_slice_lds16 for lanes whose decision variable is odd. Both increments
+// of d are even, so an odd d stays odd and is never zero: the line never
+// passes through a voxel corner (its x and y steps go in opposite directions),
+// and each step is an x step (d < 0) or a y step. 9 VALU instructions per
+// step instead of 12; the same voxels.
+__device__ __forceinline__ void walk_slice_lds16_odd(int32_t d, int32_t off, int32_t last,
+                                                     int32_t incx, int32_t incy, int32_t ox,
+                                                     int32_t oy, int32_t maxit)
+{
+    int32_t t0, t1, t2;
+    uint64_t save, sbx;
+    int32_t it = maxit;
+    asm volatile(
+        "s_mov_b64 %[save], exec\n"
+        "1:\n"
+        "v_cmp_gt_i32 %[sbx], 0, %[d]\n"
+        "v_cmp_ne_u32 vcc, %[off], %[last]\n"
+        "v_and_b32 %[t0], -4, %[off]\n"
+        "v_bfe_u32 %[t1], %[off], 1, 1\n"
+        "v_cndmask_b32 %[t2], %[incy], %[incx], %[sbx]\n"
+        "v_add_u32 %[d], %[d], %[t2]\n"
+        "v_mad_u32_u24 %[t1], %[t1], %[k16], 1\n"
+        "ds_add_u32 %[t0], %[t1]\n"
+        "v_cndmask_b32 %[t2], %[oy], %[ox], %[sbx]\n"
+        "v_add_u32 %[off], %[off], %[t2]\n"
+        "s_and_b64 exec, exec, vcc\n"
+        "s_cbranch_execz 2f\n"
+        "s_sub_u32 %[it], %[it], 1\n"
+        "s_cmp_eq_u32 %[it], 0\n"
+        "s_cbranch_scc0 1b\n"
+        "2:\n"
+        "s_mov_b64 exec, %[save]\n"
+        : [d] "+v"(d), [off] "+v"(off), [it] "+s"(it), [t0] "=&v"(t0), [t1] "=&v"(t1),
+          [t2] "=&v"(t2), [save] "=&s"(save), [sbx] "=&s"(sbx)
+        : [last] "v"(last), [incx] "v"(incx), [incy] "v"(incy), [ox] "v"(ox), [oy] "v"(oy),
+          [k16] "s"(65535)
+        : "vcc", "scc", "memory");
+}
+
 // Walk state of A_i inside z-slice k for walk_slice_lds16, set up once per
 // (line, slice) from two walk_init calls restricted to the slice (forward for
 // the first voxel and d, reversed for the last voxel): the decision
