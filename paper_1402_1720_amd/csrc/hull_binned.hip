@@ -224,7 +224,7 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                         const int64_t adx = (int64_t)q[3] - q[0], ady = (int64_t)q[4] - q[1];
                         const bool wide = max(adx < 0 ? -adx : adx, ady < 0 ? -ady : ady) >= (int64_t(1) << 19);
                         bool packs = true;
-                        for (int a = 0; a < 6; ++a) packs &= q[a] >= -kPackLimit && q[a] < kPackLimit;
+                        for (int c = 0; c < 6; ++c) packs &= q[c] >= -kPackLimit && q[c] < kPackLimit;
                         if (!tile_ok || ns > kMaxSlicesPerLine || wide || !packs) {
                             meta |= kMetaOverflow;
                             atomicAdd(&lh[w.nsub - 2 + cls], 1u);
