@@ -297,96 +297,16 @@ __device__ __forceinline__ void walk_slice_lds16_odd(int32_t d, int32_t off, int
 }
 
 // Walk state of A_i inside z-slice k for walk_slice_lds16, set up once per
-// (line, slice) from two walk_init calls restricted to the slice (forward for
-// the first voxel and d, reversed for the last voxel): the decision
-// variable, the first and the last voxel (in-plane index), |D| on x and y
-// (d changes by 2048 Ay per x step and by -2048 Ax per y step) and the step
-// directions. first = last = -1 when the line does not meet the slice inside
-// the grid. Exact when |D| < 2^19 on x and y (the int32 condition of the loop).
+// (line, slice) by walk_init's entry rule restricted to the slice (the line
+// for the first voxel and d, the reversed line for the last voxel): the
+// decision variable, the first and the last voxel (in-plane index), |D| on x
+// and y (d changes by 2048 Ay per x step and by -2048 Ax per y step) and the
+// step directions. first = last = -1 when the line does not meet the slice
+// inside the grid. Exact when |D| < 2^19 on x and y (the int32 condition of
+// the loop).
 struct SliceState {
     int32_t d, first, last, ax, ay, sx, sy;
 };
-
-// Where a line enters the box of one slice, [0, kQ nx) x [0, kQ ny) x
-// [0, kQ) in slice-local coordinates: walk_init's entry rule, keeping only
-// what the in-plane walk needs. The in-plane voxel (cx, cy); with dxy != null
-// also the x/y decision variable there. The z index is fixed by the slice,
-// so z is only range-checked, and only when check_z (the reversed line meets
-// the box whenever the line does). False when the line misses the box.
-__device__ __forceinline__ bool slice_entry(const int32_t P[3], const int32_t D[3], int nx, int ny,
-                                            bool check_z, int &cx, int &cy, int32_t *dxy)
-{
-    const int n[3] = {nx, ny, 1};
-    int32_t A[3], en[3];
-    int g[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        if (D[b] == 0 && (P[b] < 0 || P[b] >= kQ * n[b])) return false;
-        A[b] = D[b] < 0 ? -D[b] : D[b];
-        en[b] = D[b] > 0 ? -P[b] : P[b] - kQ * n[b];
-        g[b] = D[b] < 0;
-    }
-    int wa = -1;
-    int32_t ew = 0, aw = 1;
-    int gw = 0;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        if (!A[b]) continue;
-        if (wa >= 0) {
-            const int64_t l = mul64(en[b], aw), r = mul64(ew, A[b]);
-            if (!(l > r || (l == r && g[b] > gw))) continue;
-        }
-        wa = b; ew = en[b]; aw = A[b]; gw = g[b];
-    }
-    if (check_z && wa != 2 && D[2] != 0) {
-        const int64_t num = mul64(P[2], aw) + mul64(D[2], ew);
-        const int64_t lim = mul64(kQ, aw);
-        if (gw && D[2] < 0 ? (num <= 0 || num > lim) : (num < 0 || num >= lim)) return false;
-    }
-    int c[2];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        if (b == wa) {
-            c[b] = D[b] > 0 ? 0 : n[b] - 1;
-        } else if (D[b] == 0) {
-            c[b] = P[b] >> 10;
-        } else {
-            c[b] = entry_index(P[b], D[b], ew, aw, gw && D[b] < 0, n[b]);
-            if (c[b] < 0) return false;
-        }
-    }
-    cx = c[0];
-    cy = c[1];
-    if (dxy) {
-        const int32_t ex = D[0] > 0 ? kQ * (c[0] + 1) - P[0] : (D[0] < 0 ? P[0] - kQ * c[0] : 1);
-        const int32_t ey = D[1] > 0 ? kQ * (c[1] + 1) - P[1] : (D[1] < 0 ? P[1] - kQ * c[1] : 1);
-        *dxy = (int32_t)(2 * (mul64(ex, A[1]) - mul64(ey, A[0])) + (g[0] - g[1]));
-    }
-    return true;
-}
-
-__device__ __forceinline__ void slice_state(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
-                                            int nx, int ny, int k, SliceState &s)
-{
-    const int zs = k * kQ;
-    const int32_t P[3] = {qix, qiy, qiz - zs}, Q[3] = {qox, qoy, qoz - zs};
-    const int32_t D[3] = {qox - qix, qoy - qiy, qoz - qiz};
-    const int32_t R[3] = {-D[0], -D[1], -D[2]};
-    int fx, fy, lx, ly;
-    int32_t d;
-    if (!slice_entry(P, D, nx, ny, true, fx, fy, &d) ||
-        !slice_entry(Q, R, nx, ny, false, lx, ly, nullptr)) {
-        s.d = 0; s.first = -1; s.last = -1; s.ax = 0; s.ay = 0; s.sx = 1; s.sy = 1;
-        return;
-    }
-    s.d = d;
-    s.first = fx + nx * fy;
-    s.last = lx + nx * ly;
-    s.ax = D[0] < 0 ? -D[0] : D[0];
-    s.ay = D[1] < 0 ? -D[1] : D[1];
-    s.sx = D[0] > 0 ? 1 : -1;
-    s.sy = D[1] > 0 ? 1 : -1;
-}
 
 // The slice set-up in FP64. For endpoint coordinates below 2^23 in magnitude
 // (2^24 after the slice shift of at most 2047 slices) every entry distance is
