@@ -263,6 +263,55 @@ def bench_stream(torch, gen, H, h, spec, params, hist, reps=3):
     return out
 
 
+def bench_full_scale(torch, gen, H, dev, reps):
+    """The full-scale scan (256x256x64 grid, 2e8 histories at 360 angles, 2%
+    outliers): histories generated in chunks straight into device arrays
+    (6.4 GB resident), then the counting pass and hull_all with all three
+    masks, each timed with HIP events over `reps` calls."""
+    spec = gen.config_spec(3)
+    n = spec.n_hist
+    arr = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in gen.FIELDS}
+    t0 = time.time()
+    step = 20_000_000
+    for h0 in range(0, n, step):
+        h = gen.generate(spec, h0, min(n, h0 + step))
+        for k in gen.FIELDS:
+            arr[k][h0:h0 + h[k].size].copy_(torch.from_numpy(h[k]))
+    log(f"generated {n} histories in {time.time() - t0:.1f} s")
+    hist = H.Histories(arr)
+    grid = spec.grid
+    V = grid.voxels
+    params = H.make_params(wepl_low=1.0, wepl_high=5.0, msc_n_t=5, msc_mode=H.HULL_MSC_COUNT,
+                           sm_frac_num=3, sm_frac_den=5, sm_mode=H.HULL_SM_FRACTION)
+    N = torch.zeros(V, dtype=torch.int32, device=dev)
+    M = torch.zeros(V, dtype=torch.int32, device=dev)
+    masks = [torch.zeros(V, dtype=torch.uint8, device=dev) for _ in range(3)]
+    ws = H.workspace(H.HULL_OP_ALL, grid, n, dev)
+    st = torch.zeros(6, dtype=torch.int64, device=dev)
+    s = torch.cuda.current_stream()
+    H.hull_all(hist, grid, params, N, M, *masks, stats=st, ws=ws, stream=s)
+    torch.cuda.synchronize()
+    stats = H.stats_dict(st)
+    visits = stats["n_visits_low"] + stats["n_visits_high"]
+    out = {"workload": "full-scale head phantom 256x256x64 (0.78125x0.78125x2.5 mm), 2e8 "
+                       "histories, 360 angles, sigma 3 mm + 2% outliers; SC+MSC+SM one pass",
+           "histories": n, "voxel_visits": visits, "stats": stats}
+    for name, fn in (("counting_pass", lambda: H.hull_all(hist, grid, params, N, M,
+                                                          flags=H.HULL_ACCUMULATE, ws=ws,
+                                                          stream=s)),
+                     ("hull_all", lambda: H.hull_all(hist, grid, params, N, M, *masks, ws=ws,
+                                                     stream=s))):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        for _ in range(reps):
+            fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[name] = {"ms": ms, "histories_per_s": n / (ms * 1e-3), "visits_per_s": visits / (ms * 1e-3)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +326,9 @@ def main():
                          "up to 1e7")
     ap.add_argument("--bsc-only", action="store_true",
                     help="time the binned SC alone (for a profile of its kernels)")
+    ap.add_argument("--full-scale", action="store_true",
+                    help="time the full-scale scan instead (256x256x64, 2e8 histories, 360 "
+                         "angles, generated on the device in chunks): counting pass and hull_all")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one 256 MiB device-to-device copy: the "
                          "known-size kernel that scales hardware byte counters")
@@ -292,6 +344,9 @@ def main():
     from paper_1402_1720_amd import hullmi as H
 
     dev = torch.device("cuda:0")
+    if args.full_scale:
+        bench_full_scale(torch, gen, H, dev, max(1, args.steps))
+        return
     spec = gen.config_spec(2)
     geo = spec.fbp_geometry(du=1.0, dv=5.0)
     t0 = time.time()
