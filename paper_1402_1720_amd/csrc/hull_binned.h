@@ -1,8 +1,10 @@
 // Slice-binned counting: the (history, z-slice) items of a batch are sorted by
-// (class, slice, length class), each stored with its line's endpoints; a persistent grid of workgroups takes
-// contiguous ranges of equal estimated work from that list and accumulates
-// each slice it meets in a 16-bit LDS copy, written out as a partial tile when
-// its range leaves the slice; a reduction then adds the partials into N or M.
+// (class, slice, length class), each a 16-byte record (the line's packed
+// endpoints, then its packed slice-walk state); a persistent grid of
+// workgroups takes ranges of equal estimated work from that list (two per
+// workgroup, dealt round-robin) and accumulates each slice it meets in a
+// 16-bit LDS copy, written out as a partial tile when its range leaves the
+// slice; a reduction then adds the partials into N or M.
 #pragma once
 
 #include <hip/hip_runtime.h>
