@@ -134,6 +134,21 @@ def test_sums_of_squares_beyond_64_bits():
     assert r["stats"]["n_cut"] == 3
 
 
+def test_distant_source_takes_the_integer_set_up():
+    """A source 20 m away: the bin lines' coordinates exceed 2^23 (1/1024
+    voxel), beyond the exact FP64 slice set-up, so the carve takes the
+    64-bit integer one; same result as the oracle."""
+    spec = gen.config_spec(1, n_hist=200_000)
+    h = gen.generate(spec)
+    geo = spec.fbp_geometry(du=1.0, dv=2.5)
+    geo = gen.FbpGeometry(src_dist=20000.0, du=geo.du, dv=geo.dv, nu=geo.nu, nv=geo.nv,
+                          u0=geo.u0, v0=geo.v0, n_angles=geo.n_angles, angle0=geo.angle0,
+                          dangle=geo.dangle)
+    assert 20000.0 / spec.grid.d[0] * 1024 > 2 ** 23
+    g, r = run_both(h, spec.grid, geo, what="distant source")
+    assert r["stats"]["n_bins_carved"] > 0
+
+
 def test_detector_plane_beyond_the_lds():
     """Fine bins: a detector plane of 16-byte sums larger than the LDS turns
     the per-chunk planes of the first pass off; 8-byte kept sums still fit
