@@ -149,8 +149,23 @@ size_t allow_max_lds(const void *fn, size_t max_lds)
 
 inline int64_t plane_of(const hullmi_grid *g) { return (int64_t)g->nx * g->ny; }
 
-// A slice fits the LDS tile when its 16-bit counters fit kMaxTileVoxels.
-inline bool tile_fits(const hullmi_grid *g) { return plane_of(g) <= kMaxTileVoxels; }
+// Counters per tile row: nx rounded up to even, plus 2 when half of that is
+// even, so that a row holds an odd number of LDS words and neighbouring rows
+// start in different banks; not padded when that would cost the second walk
+// workgroup on a CU.
+inline int tile_stride(const hullmi_grid *g)
+{
+    const int e = (g->nx + 1) & ~1;
+    const int s = (e / 2) % 2 ? e : e + 2;
+    const int64_t two = 2 * (2 * (int64_t)s * g->ny + 16), two_e = 2 * (2 * (int64_t)e * g->ny + 16);
+    return two <= 160 * 1024 || two_e > 160 * 1024 ? s : e;
+}
+// A slice fits the LDS tile when its 16-bit counters, padded rows included,
+// fit kMaxTileHalfwords.
+inline bool tile_fits(const hullmi_grid *g)
+{
+    return (int64_t)tile_stride(g) * g->ny <= kMaxTileHalfwords;
+}
 
 // Length classes per slice: up to 16, fewer when there are many slices, so
 // that the sub-bin histogram of a block fits its LDS.
@@ -176,7 +191,9 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.ntiles = 2 * g->nz;
     w.nsub = w.ntiles * w.nl + 2;
     w.nblk = (int)((B + kHistPerBlock - 1) / kHistPerBlock);
-    w.tile_words = tile_fits(g) ? (int)((plane_of(g) + 1) / 2) : 1;
+    w.stride = tile_stride(g);
+    w.gnx = g->nx;
+    w.tile_words = tile_fits(g) ? (int)((int64_t)w.stride * g->ny / 2) : 1;
     w.min_ranges = kMaxWalkGroups * kRangesPerGroup;
     // ranges: P0 = max(min_ranges, ceil(I / kItemsPerRange)) coarse ranges,
     // each split into at most ceil(items / kItemsPerRange) pieces:

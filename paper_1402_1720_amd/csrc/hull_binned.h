@@ -21,7 +21,7 @@ constexpr int kHistPerBlock = kBinThreads * kHistPerThread;
 constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic walk
 constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
 constexpr int kTileThreads = 1024;      // workgroup of the LDS walk
-constexpr int kMaxTileVoxels = 65536;   // 16-bit counters: 128 KB of LDS
+constexpr int kMaxTileHalfwords = (160 * 1024 - 16) / 2;   // 16-bit counters, 160 KB of LDS
 constexpr int kItemsPerRange = 65535;   // a range holds at most this many items: each adds
                                         // at most 1 to a voxel, so a 16-bit counter holds it
 constexpr int kWorkPerItem = 16;        // fixed cost of an item in visit units (set-up)
@@ -60,6 +60,7 @@ struct BinWs {
     uint32_t *partial;      // [max_slots][tile_words]
     int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
     int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;
+    int stride, gnx;        // tile row length in counters (padded), grid columns
     int64_t B;
 };
 

@@ -97,17 +97,19 @@ __device__ __forceinline__ void unpack_line(const uint4 r, int q[6])
     q[3] = g(hi, 0); q[4] = g(hi, 21); q[5] = g(hi, 42);
 }
 
-// Slice-walk state in 16 bytes: d; the first and the last voxel of the slice
-// part (16 bits each, a slice tile has at most 65536 voxels); |Dy| and |Dx|
-// (below 2^19 on a tile line), the signs of the x and y steps and a flag for a
-// slice the line does not meet.
+// Slice-walk state in 16 bytes: d; the tile counters of the first and the
+// last voxel of the slice part (17 bits each, a tile has at most 81912
+// counters: the low 16 bits in the second word, bit 16 in bits 22 and 23 of
+// the third); |Dy| and |Dx| (below 2^19 on a tile line), the signs of the x
+// and y steps and a flag for a slice the line does not meet.
 constexpr uint32_t kStateEmpty = 1u << 21;
 
 __device__ __forceinline__ uint4 pack_state(const SliceState &s)
 {
     if (s.first < 0) return make_uint4(0u, 0u, kStateEmpty, 0u);
-    return make_uint4((uint32_t)s.d, (uint32_t)s.first | (uint32_t)s.last << 16,
-                      (uint32_t)s.ay | (uint32_t)(s.sx < 0) << 19 | (uint32_t)(s.sy < 0) << 20,
+    return make_uint4((uint32_t)s.d, ((uint32_t)s.first & 0xffffu) | (uint32_t)s.last << 16,
+                      (uint32_t)s.ay | (uint32_t)(s.sx < 0) << 19 | (uint32_t)(s.sy < 0) << 20 |
+                          ((uint32_t)s.first >> 16) << 22 | ((uint32_t)s.last >> 16) << 23,
                       (uint32_t)s.ax);
 }
 
@@ -463,7 +465,7 @@ __global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
         int q[6];
         unpack_line(cur, q);
         SliceState st;
-        slice_state_tile(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, t % w.nz, st);
+        slice_state_tile(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, w.stride, t % w.nz, st);
         w.item[p] = pack_state(st);
     }
 }
@@ -506,9 +508,9 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
                 const int32_t incx = (int32_t)((a.z & 0x7ffffu) << 11);
                 const int32_t incy = -(int32_t)(a.w << 11);
                 const int32_t ox = (a.z >> 19) & 1u ? -2 : 2;
-                const int32_t oy = (a.z >> 20) & 1u ? -2 * nx : 2 * nx;
-                const int32_t off = (int32_t)(tile_base + 2 * (a.y & 0xffffu));
-                const int32_t last = (int32_t)(tile_base + 2 * (a.y >> 16));
+                const int32_t oy = (a.z >> 20) & 1u ? -2 * w.stride : 2 * w.stride;
+                const int32_t off = (int32_t)(tile_base + 2 * ((a.y & 0xffffu) | ((a.z >> 22) & 1u) << 16));
+                const int32_t last = (int32_t)(tile_base + 2 * ((a.y >> 16) | ((a.z >> 23) & 1u) << 16));
                 // lines of one wave mostly share their step directions: when
                 // every live lane's d is odd (no corner can be hit), the wave
                 // takes the shorter loop
@@ -588,9 +590,12 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N
     }
     int *dst = cls ? M : N;
     if (wd < w.tile_words) {
-        const int64_t v0 = (int64_t)k * plane + 2 * wd;
-        dst[v0] += (int)lo;
-        if (2 * wd + 1 < plane) dst[v0 + 1] += (int)hi;
+        // counters 2 wd and 2 wd + 1 lie in one tile row (rows hold an even
+        // number of counters); those past column nx - 1 are padding
+        const int y = 2 * wd / w.stride, x = 2 * wd - y * w.stride;
+        const int64_t v0 = (int64_t)k * plane + (int64_t)y * w.gnx + x;
+        if (x < w.gnx) dst[v0] += (int)lo;
+        if (x + 1 < w.gnx) dst[v0 + 1] += (int)hi;
     }
     if (st) {
         const unsigned long long v = block_sum((unsigned long long)lo + hi, red);

@@ -299,7 +299,8 @@ __device__ __forceinline__ void walk_slice_lds16_odd(int32_t d, int32_t off, int
 // Walk state of A_i inside z-slice k for walk_slice_lds16, set up once per
 // (line, slice) by walk_init's entry rule restricted to the slice (the line
 // for the first voxel and d, the reversed line for the last voxel): the
-// decision variable, the first and the last voxel (in-plane index), |D| on x
+// decision variable, the first and the last voxel (in-plane index x + stride
+// y, stride >= nx being the length of a tile row), |D| on x
 // and y (d changes by 2048 Ay per x step and by -2048 Ax per y step) and the
 // step directions. first = last = -1 when the line does not meet the slice
 // inside the grid. Exact when |D| < 2^19 on x and y (the int32 condition of
@@ -382,7 +383,7 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
 }
 
 __device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
-                                                 int nx, int ny, int k, SliceState &s)
+                                                 int nx, int ny, int stride, int k, SliceState &s)
 {
     const int zs = k * kQ;
     const int32_t P[3] = {qix, qiy, qiz - zs}, Q[3] = {qox, qoy, qoz - zs};
@@ -396,8 +397,8 @@ __device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int 
         return;
     }
     s.d = (int32_t)d;   // below 2^31 in magnitude on a tile line
-    s.first = fx + nx * fy;
-    s.last = lx + nx * ly;
+    s.first = fx + stride * fy;
+    s.last = lx + stride * ly;
     s.ax = D[0] < 0 ? -D[0] : D[0];
     s.ay = D[1] < 0 ? -D[1] : D[1];
     s.sx = D[0] > 0 ? 1 : -1;

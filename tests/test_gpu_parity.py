@@ -349,6 +349,32 @@ def test_grid_wider_than_a_tile():
     assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
 
 
+@pytest.mark.parametrize("shape", [(256, 256, 6), (204, 200, 4), (255, 300, 3)])
+def test_padded_tile_rows(shape):
+    """LDS tile rows padded to an odd number of words (256 -> 258 and
+    255 -> 258 counters, so counters past 65535 are addressed), and a grid
+    whose padding would cost the second walk workgroup on a CU (204 columns,
+    not padded): same counts as the oracle, including lines through the last
+    rows and columns."""
+    rng = np.random.default_rng(31)
+    g = gen.Grid(shape, (1.0, 1.0, 2.0))
+    half = np.array(g.half)
+    n = 30_000
+    h = _random_histories(rng, n, half[2] * 0.9, half[1] * 1.05)
+    h["x_in"] = np.full(n, -half[0] - 2.0, np.float32)
+    h["x_out"] = np.full(n, half[0] + 2.0, np.float32)
+    edge = rng.random(n) < 0.3   # lines along the last rows
+    h["y_in"] = np.where(edge, half[1] - rng.uniform(0.0, 3.0, n), h["y_in"]).astype(np.float32)
+    h["y_out"] = np.where(edge, half[1] - rng.uniform(0.0, 3.0, n), h["y_out"]).astype(np.float32)
+    h["angle_deg"] = np.where(edge, 0.0, h["angle_deg"]).astype(np.float32)
+    G = oracle.grid_of(g)
+    rN, rM, rst = oracle.counts(h, G)
+    gN, gM, gst = gpu_counts(h, g)
+    assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
+    vol = rN.reshape(shape[2], shape[1], shape[0])
+    assert vol[:, -1, :].sum() > 0 and vol[:, :, -1].sum() > 0
+
+
 def test_lines_through_grid_corners_edges_and_faces():
     """Lines through a corner, along an edge or within a face of the grid box
     (and through inner voxel corners): the FP32 slab cannot decide these, so
