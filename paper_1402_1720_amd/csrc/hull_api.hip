@@ -316,7 +316,9 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         k_bin_plan<<<1, 1024, 0, s>>>(wb);
         k_bin_scatter<<<wb.nblk, kBinThreads, 0, s>>>(nb, wb);
         if (tile_ok) {
-            k_item_setup<<<dp.cus * 8, 256, (size_t)(wb.ntiles + 1) * 4, s>>>(wb, g->nx, g->ny);
+            // 16 blocks per CU: 125 us against 131 us with 8 and 153 us with 4
+            // (1.1e7 items, 200x200x32)
+            k_item_setup<<<dp.cus * 16, 256, (size_t)(wb.ntiles + 1) * 4, s>>>(wb, g->nx, g->ny);
             k_walk_tiles<<<walk_grid, kTileThreads, tile_bytes, s>>>(wb, g->nx, g->ny);
             dim3 rg((unsigned)((wb.tile_words + 255) / 256), (unsigned)wb.ntiles);
             k_reduce_tiles<<<rg, 256, 0, s>>>(wb, plane, N, M, stats);
