@@ -154,12 +154,20 @@ class ScanSpec:
 
 
 def head_phantom(grid: Grid, inserts: bool = False,
-                 scale: Tuple[float, float, float] = (1.0, 1.0, 1.0)) -> Tuple[Ellipsoid, ...]:
+                 scale: Tuple[float, float, float] = (1.0, 1.0, 1.0),
+                 ventricles: bool = False) -> Tuple[Ellipsoid, ...]:
     """Nested-ellipsoid head: skull shell (RSP 1.6) around brain (RSP 1.04), the
     paper's tissue values (Section 2.1). Skull semi-axes are (0.62, 0.78, 0.90)
     of the grid half-extents; at a 200 mm field that is a 15,193 mm^2 central
     slice, within 1% of the paper's 15,336-voxel phantom slice (Section 4.1).
-    Optional inserts: three 1 cm ellipsoids of RSP 0.3, 1.1 and 1.8 in the brain."""
+    Optional inserts: three 1 cm ellipsoids of RSP 0.3, 1.1 and 1.8 in the brain.
+    Optional ventricles: the paper's phantom also holds two fluid-filled
+    ventricles of RSP 0.9 inside the brain (Section 2.1; their size and place
+    are not given): ellipsoids of semi-axes (0.12, 0.30, 0.30) of the brain's,
+    centred at (+-0.22 a, 0.08 b, 0.05 c) of the brain semi-axes (a, b, c),
+    elongated front to back like lateral ventricles and apart from each other.
+    Ventricles and inserts are meant to be used one at a time (they would
+    overlap)."""
     hx, hy, hz = grid.half
     sx, sy, sz = scale
     a, b, c = 0.62 * hx * sx, 0.78 * hy * sy, 0.90 * hz * sz
@@ -171,7 +179,20 @@ def head_phantom(grid: Grid, inserts: bool = False,
         for (cx, cy), rho in (((0.35 * ab, 0.25 * bb), 0.3), ((-0.35 * ab, 0.25 * bb), 1.1),
                               ((0.0, -0.35 * bb), 1.8)):
             ells.append(Ellipsoid((cx, cy, 0.0), (5.0, 4.0, 5.0), rho - 1.04))
+    if ventricles:
+        for side in (1.0, -1.0):
+            ells.append(Ellipsoid((side * 0.22 * ab, 0.08 * bb, 0.05 * cb),
+                                  (0.12 * ab, 0.30 * bb, 0.30 * cb), 0.9 - 1.04))
     return tuple(ells)
+
+
+def ventricle_spec(n_hist: int = 10_000_000, seed_offset: int = 0) -> ScanSpec:
+    """The paper's simulated head (skull, brain, two ventricles of RSP 0.9,
+    Section 2.1) on the 200x200x32 grid of 1x1x3 mm voxels (the paper's FDK
+    volume, Section 3.1), 180 gantry angles, WEPL noise 3 mm; seed 0x5EED0006."""
+    g = Grid((200, 200, 32), (1.0, 1.0, 3.0))
+    return ScanSpec(g, int(n_hist), 180, head_phantom(g, ventricles=True),
+                    0x5EED0006 + seed_offset, sigma=3.0)
 
 
 def sphere_phantom(radius: float, rho: float = 1.0,

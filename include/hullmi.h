@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define HULLMI_ABI_VERSION 2
+#define HULLMI_ABI_VERSION 3
 
 typedef enum hull_status {
     HULL_OK = 0,
@@ -280,6 +280,45 @@ int hull_count_lines(const int32_t *q_in, const int32_t *q_out, int64_t n,
                      const hullmi_grid *grid, int32_t *counts, uint32_t flags,
                      hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* Kernels (or short groups of launches) as hull_count_profile and
+ * hull_fbp_profile report them. */
+enum hull_prof_kernel {
+    HULL_PROF_CLASSIFY = 0,       /* classes, geometry, slice ranges, per-block bin counts */
+    HULL_PROF_SCAN = 1,           /* per-bin offsets of every block */
+    HULL_PROF_PLAN = 2,           /* bin and slice starts, equal-work ranges */
+    HULL_PROF_SCATTER = 3,        /* (history, slice) items in bin order */
+    HULL_PROF_SETUP = 4,          /* slice-walk state of every item */
+    HULL_PROF_WALK = 5,           /* the voxel walk into LDS slice tiles */
+    HULL_PROF_REDUCE = 6,         /* partial tiles summed into N and M */
+    HULL_PROF_OVERFLOW = 7,       /* lines over many slices, global atomics */
+    HULL_PROF_FBP_CLEAR = 8,      /* FDK: zero the bin sums and counts */
+    HULL_PROF_FBP_BIN = 9,        /* FDK: bin every history on the detector */
+    HULL_PROF_FBP_FILTER = 10,    /* FDK: weight and Shepp-Logan filter every row */
+    HULL_PROF_FBP_GEOMETRY = 11,  /* FDK: per-angle trig and per-tile footprints */
+    HULL_PROF_FBP_BACKPROJECT = 12, /* FDK: backprojection and threshold */
+    HULL_PROF_KERNELS = 13
+};
+
+/* Measurement aid: the counting pass of hull_all (no masks) with a HIP event
+ * pair recorded around every kernel launch on `stream`. Arguments, flags and
+ * errors as hull_all (N and M required). The call waits for the stream;
+ * then ms[k] (host, HULL_PROF_KERNELS entries) holds the summed duration of
+ * kernel k over every internal batch of 2^24 histories and launches[k] (host,
+ * may be NULL) the number of its launches. The counts equal hull_all's.
+ * HULL_EDEVICE also when an event cannot be created or read. */
+int hull_count_profile(const hullmi_histories *hist, const hullmi_grid *grid,
+                       const hullmi_params *params, int32_t *N, int32_t *M, uint32_t flags,
+                       hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream, float *ms,
+                       int32_t *launches);
+
+/* Measurement aid: hull_fbp with a HIP event pair around every kernel launch
+ * (or group of launches) on `stream`; waits for the stream and fills ms and
+ * launches as hull_count_profile does (entries HULL_PROF_FBP_*). Arguments
+ * and errors as hull_fbp. */
+int hull_fbp_profile(const hullmi_histories *hist, const hullmi_grid *grid,
+                     const hullmi_fbp_params *fbp, float *image, uint8_t *mask, void *ws,
+                     size_t ws_bytes, void *stream, float *ms, int32_t *launches);
+
 /* The geometry step alone: per history status (0 ok, 1 non-finite field,
  * 2 endpoint out of range, 3 degenerate) and the quantised endpoints [n][3]
  * (int32, 1/1024 voxel; left unwritten for status 1 and 2). */
@@ -385,14 +424,27 @@ typedef struct hullmi_job {
     hullmi_bsc_stats *bsc_stats;
 } hullmi_job;
 
-/* Launch choices of a plan. streams: concurrent internal streams (1..16);
+/* Launch choices of a plan; counts and masks do not depend on any of them.
+ * streams: concurrent internal streams (1..16);
  * use_graph: capture on the first launch and replay afterwards (0 / 1);
  * walk_blocks: cap on the workgroups of each persistent walk (0 = one per
- * resident slot of the device). */
+ *   resident slot of the device);
+ * ranges_per_group: ranges of equal estimated work dealt to each walk
+ *   workgroup (0..64; 0 = 2 where two walk workgroups share a CU, 8 where one
+ *   fills it; never more than 2048 / walk workgroups);
+ * length_classes: line-length classes per z-slice by which the walk's items
+ *   are grouped so that a wavefront walks lines of similar length (0..16;
+ *   0 = 16, or fewer on grids of more than 128 slices);
+ * run_stride: the item runs of one (class, slice, length) bin are ordered
+ *   by classification block modulo this stride, so that neighbouring runs
+ *   come from histories of different gantry angles (0..256; 0 = 8). */
 typedef struct hullmi_tuning {
     int32_t streams;
     int32_t use_graph;
     int32_t walk_blocks;
+    int32_t ranges_per_group;
+    int32_t length_classes;
+    int32_t run_stride;
 } hullmi_tuning;
 
 typedef struct hullmi_plan hullmi_plan;

@@ -153,23 +153,37 @@ inline int64_t plane_of(const hullmi_grid *g) { return (int64_t)g->nx * g->ny; }
 // even, so that a row holds an odd number of LDS words and neighbouring rows
 // start in different banks; not padded when that would cost the second walk
 // workgroup on a CU.
+// LDS bytes of a walk workgroup for tile rows of `stride` counters: the tile
+// rounded up to whole 16-byte quads (the flush and the reduce move four words
+// at a time), then the control words.
+inline int64_t tile_lds_bytes(int64_t stride, int ny)
+{
+    return ((stride * ny / 2 + 3) & ~int64_t(3)) * 4 + 16;
+}
 inline int tile_stride(const hullmi_grid *g)
 {
     const int e = (g->nx + 1) & ~1;
     const int s = (e / 2) % 2 ? e : e + 2;
-    const int64_t two = 2 * (2 * (int64_t)s * g->ny + 16), two_e = 2 * (2 * (int64_t)e * g->ny + 16);
+    const int64_t two = 2 * tile_lds_bytes(s, g->ny), two_e = 2 * tile_lds_bytes(e, g->ny);
     return two <= 160 * 1024 || two_e > 160 * 1024 ? s : e;
 }
 // A slice fits the LDS tile when its 16-bit counters, padded rows included,
-// fit kMaxTileHalfwords.
+// fit the 160 KB of LDS.
 inline bool tile_fits(const hullmi_grid *g)
 {
-    return (int64_t)tile_stride(g) * g->ny <= kMaxTileHalfwords;
+    return tile_lds_bytes(tile_stride(g), g->ny) <= 160 * 1024;
 }
 
 // Length classes per slice: up to 16, fewer when there are many slices, so
-// that the sub-bin histogram of a block fits its LDS.
+// that the sub-bin histogram of a block fits its LDS. The workspace is laid
+// out for this many; a tuning may ask for fewer.
 inline int length_classes(const hullmi_grid *g) { return std::max(1, std::min(16, 2048 / g->nz)); }
+
+// Length-class width (voxels of in-plane extent) for nl classes per slice.
+inline int length_width(const hullmi_grid *g, int nl) { return std::max(1, (g->nx + g->ny + nl - 1) / nl); }
+
+// Runs of a sub-bin are ordered by classification block modulo this stride.
+constexpr int kDefaultRunStride = 8;
 
 // Workgroups of the persistent walk at most, and ranges per workgroup: the
 // ranges of equal estimated work are dealt out round-robin, and two per
@@ -193,13 +207,15 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.B = B;
     w.nz = g->nz;
     w.nl = length_classes(g);
-    w.lwidth = std::max(1, (g->nx + g->ny + w.nl - 1) / w.nl);
+    w.lwidth = length_width(g, w.nl);
     w.ntiles = 2 * g->nz;
     w.nsub = w.ntiles * w.nl + 2;
     w.nblk = (int)((B + kHistPerBlock - 1) / kHistPerBlock);
     w.stride = tile_stride(g);
     w.gnx = g->nx;
+    w.run_stride = kDefaultRunStride;
     w.tile_words = tile_fits(g) ? (int)((int64_t)w.stride * g->ny / 2) : 1;
+    w.slot_words = (w.tile_words + 3) & ~3;
     w.min_ranges = kMaxWalkGroups * kRangesPerGroup;
     // ranges: P0 = max(min_ranges, ceil(I / kItemsPerRange)) coarse ranges,
     // each split into at most ceil(items / kItemsPerRange) pieces:
@@ -231,7 +247,7 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.ctl = reinterpret_cast<int32_t *>(take((size_t)kCtlWords * 4));
     w.item = reinterpret_cast<uint4 *>(take((size_t)imax * 16));
     w.partial = reinterpret_cast<uint32_t *>(
-        take(tile_fits(g) ? (size_t)w.max_slots * w.tile_words * 4 : 0));
+        take(tile_fits(g) ? (size_t)w.max_slots * w.slot_words * 4 : 0));
     if (bytes) *bytes = off;
     return w;
 }
@@ -285,7 +301,7 @@ FbpWs fbp_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, void *base
 // Histories go through in batches of up to kBatch; counts add up across them.
 int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, float e_high, int32_t *N,
                int32_t *M, uint32_t flags, hullmi_stats *stats, void *ws, hipStream_t s,
-               int walk_blocks)
+               const CountOpts &o)
 {
     const int64_t V = voxels(g);
     if (!(flags & HULL_ACCUMULATE)) {
@@ -296,7 +312,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
     if (h->n == 0) return launch_status();
     BinWs w = bin_ws_layout(g, h->n, ws, nullptr);
     const DevProps dp = dev_props();
-    const size_t tile_bytes = (size_t)w.tile_words * 4 + 16;   // tile + control words
+    const size_t tile_bytes = (size_t)tile_lds_bytes(w.stride, g->ny);   // tile + control words
     const bool tile_ok =
         tile_fits(g) &&
         tile_bytes <= allow_max_lds(reinterpret_cast<const void *>(k_walk_tiles), dp.max_lds);
@@ -308,9 +324,20 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
             per_cu = occ;
     }
     int walk_grid = std::min(dp.cus * per_cu, kMaxWalkGroups);
-    if (walk_blocks > 0) walk_grid = std::min(walk_grid, walk_blocks);
-    const int rpg = std::max(1, std::min(per_cu >= 2 ? kRangesPerGroup : kRangesPerGroupAlone,
-                                         kMaxWalkGroups * kRangesPerGroup / walk_grid));
+    if (o.walk_blocks > 0) walk_grid = std::min(walk_grid, o.walk_blocks);
+    const int rpg_want = o.ranges_per_group > 0 ? o.ranges_per_group
+                                                : (per_cu >= 2 ? kRangesPerGroup : kRangesPerGroupAlone);
+    const int rpg = std::max(1, std::min(rpg_want, kMaxWalkGroups * kRangesPerGroup / walk_grid));
+    // measurement: an event pair around every launch when asked for
+    auto mark = [&](int k) { if (o.prof) o.prof->begin(k, s); };
+    auto done = [&]() { if (o.prof) o.prof->end(s); };
+    if (o.length_classes > 0 && o.length_classes < w.nl) {
+        // fewer sub-bins than the workspace is laid out for
+        w.nl = o.length_classes;
+        w.lwidth = length_width(g, w.nl);
+        w.nsub = w.ntiles * w.nl + 2;
+    }
+    if (o.run_stride > 0) w.run_stride = o.run_stride;
     const DevGrid dg = dev_grid(g);
     const int plane = (int)plane_of(g);
     for (int64_t h0 = 0; h0 < h->n; h0 += w.B) {
@@ -318,20 +345,36 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         BinWs wb = w;
         wb.nblk = (int)((nb + kHistPerBlock - 1) / kHistPerBlock);
         wb.min_ranges = rpg * walk_grid;
+        mark(HULL_PROF_CLASSIFY);
         k_bin_classify<<<wb.nblk, kBinThreads, 0, s>>>(*h, h0, nb, dg, e_low, e_high, N != nullptr,
                                                        M != nullptr, tile_ok ? 1 : 0, wb, stats);
+        done();
+        mark(HULL_PROF_SCAN);
         k_bin_scan_blocks<<<wb.nsub, 256, 0, s>>>(wb);
+        done();
+        mark(HULL_PROF_PLAN);
         k_bin_plan<<<1, 1024, 0, s>>>(wb);
+        done();
+        mark(HULL_PROF_SCATTER);
         k_bin_scatter<<<wb.nblk, kBinThreads, 0, s>>>(nb, wb);
+        done();
         if (tile_ok) {
             // 16 blocks per CU: 125 us against 131 us with 8 and 153 us with 4
             // (1.1e7 items, 200x200x32)
+            mark(HULL_PROF_SETUP);
             k_item_setup<<<dp.cus * 16, 256, (size_t)(wb.ntiles + 1) * 4, s>>>(wb, g->nx, g->ny);
+            done();
+            mark(HULL_PROF_WALK);
             k_walk_tiles<<<walk_grid, kTileThreads, tile_bytes, s>>>(wb, g->nx, g->ny);
-            dim3 rg((unsigned)((wb.tile_words + 255) / 256), (unsigned)wb.ntiles);
+            done();
+            dim3 rg((unsigned)((wb.slot_words / 4 + 255) / 256), (unsigned)wb.ntiles);
+            mark(HULL_PROF_REDUCE);
             k_reduce_tiles<<<rg, 256, 0, s>>>(wb, plane, N, M, stats);
+            done();
         }
+        mark(HULL_PROF_OVERFLOW);
         k_walk_overflow<<<1024, 256, 0, s>>>(wb, g->nx, g->ny, g->nz, N, M, stats);
+        done();
         const int rc = launch_status();
         if (rc != HULL_OK) return rc;
     }
@@ -403,11 +446,11 @@ bool sm_args_ok(int num, int den, int mode, int scope, int nbr)
 
 int sc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t *N,
             uint8_t *mask, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
-            hipStream_t s, int walk_blocks)
+            hipStream_t s, const CountOpts &o)
 {
     if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low)) return HULL_EINVAL;
     if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, walk_blocks);
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, o);
     if (rc != HULL_OK) return rc;
     if (mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, mask, voxels(grid));
     return launch_status();
@@ -415,13 +458,13 @@ int sc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_lo
 
 int msc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t n_t,
              int mode, int nbr, int32_t *N, uint8_t *mask, uint32_t flags, hullmi_stats *stats,
-             void *ws, size_t ws_bytes, hipStream_t s, int walk_blocks)
+             void *ws, size_t ws_bytes, hipStream_t s, const CountOpts &o)
 {
     if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low) ||
         !msc_args_ok(n_t, mode, nbr))
         return HULL_EINVAL;
     if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, walk_blocks);
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, o);
     if (rc != HULL_OK) return rc;
     return run_msc_mask(grid, N, mask, n_t, mode, nbr, s);
 }
@@ -429,14 +472,14 @@ int msc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_l
 int sm_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_high, int32_t frac_num,
             int32_t frac_den, int mode, int scope, int nbr, int32_t *M, uint8_t *mask,
             uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, hipStream_t s,
-            int walk_blocks)
+            const CountOpts &o)
 {
     if (!hist_ok(hist) || !grid_ok(grid) || !M || !std::isfinite(wepl_high) ||
         !sm_args_ok(frac_num, frac_den, mode, scope, nbr))
         return HULL_EINVAL;
     const size_t cw = counts_ws_bytes(grid, hist->n);
     if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, ws, s, walk_blocks);
+    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, ws, s, o);
     if (rc != HULL_OK) return rc;
     return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr,
                        reinterpret_cast<char *>(ws) + cw, s);
@@ -445,7 +488,7 @@ int sm_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_hi
 int all_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
              int32_t *N, int32_t *M, uint8_t *sc_mask, uint8_t *msc_mask, uint8_t *sm_mask,
              uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, hipStream_t s,
-             int walk_blocks)
+             const CountOpts &o)
 {
     if (!hist_ok(hist) || !grid_ok(grid) || !p || !N || !M) return HULL_EINVAL;
     if (!std::isfinite(p->wepl_low) || !std::isfinite(p->wepl_high)) return HULL_EINVAL;
@@ -454,8 +497,7 @@ int all_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
         return HULL_EINVAL;
     const size_t cw = counts_ws_bytes(grid, hist->n);
     if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, ws, s,
-                        walk_blocks);
+    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, ws, s, o);
     if (rc != HULL_OK) return rc;
     if (sc_mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, sc_mask, voxels(grid));
     rc = launch_status();
@@ -482,16 +524,21 @@ FbpDev fbp_dev(const hullmi_fbp_params *fbp)
 // `unit` mm) and counts: the FDK steps after the binning.
 void fbp_reconstruct(const hullmi_grid *grid, const FbpDev &p, const FbpWs &w,
                      const unsigned long long *sum, const unsigned *cnt, double unit, float *image,
-                     uint8_t *mask, hipStream_t s)
+                     uint8_t *mask, hipStream_t s, KernelProf *prof = nullptr)
 {
+    auto mark = [&](int k) { if (prof) prof->begin(k, s); };
+    auto done = [&]() { if (prof) prof->end(s); };
     // the kernel table and one row per wavefront of the block (up to 98 KB
     // for 2048 bins per row, above the default dynamic LDS limit)
     const size_t lds = (size_t)(2 * p.nu + kFbpFilterRows * p.nu) * sizeof(double);
     allow_max_lds(reinterpret_cast<const void *>(k_fbp_filter), dev_props().max_lds);
+    mark(HULL_PROF_FBP_FILTER);
     fill_u32(w.q, 0u, (int64_t)w.qn, s);   // zero borders of the padded projections
     const int64_t rows = (int64_t)p.n_angles * p.nv;
     k_fbp_filter<<<(unsigned)((rows + kFbpFilterRows - 1) / kFbpFilterRows), 64 * kFbpFilterRows, lds,
                    s>>>(sum, cnt, w.q, p, unit);
+    done();
+    mark(HULL_PROF_FBP_GEOMETRY);
     k_fbp_trig<<<(p.n_angles + 63) / 64, 64, 0, s>>>(w.cs, p);
     FbpGridDev gd{grid->nx, grid->ny, grid->nz, grid->dx, grid->dy, grid->dz,
                   grid->x0, grid->y0, grid->z0};
@@ -499,41 +546,51 @@ void fbp_reconstruct(const hullmi_grid *grid, const FbpDev &p, const FbpWs &w,
     const int64_t ntiles = bp_tiles(grid, ntx, nty, ntz);
     k_fbp_footprint<<<blocks_for(ntiles * p.n_angles), kBlock, 0, s>>>(w.cs, p, gd, w.fp, ntx, nty,
                                                                        ntz);
+    done();
+    mark(HULL_PROF_FBP_BACKPROJECT);
     k_fbp_backproject_tiles<<<(unsigned)ntiles, kBpTile * kBpTile, 0, s>>>(w.q, w.cs, w.fp, p, gd,
                                                                           image, mask, ntx, nty);
+    done();
 }
 
-void fbp_bin_stage(const hullmi_histories *hist, const FbpDev &p, const FbpWs &w, hipStream_t s);
+void fbp_bin_stage(const hullmi_histories *hist, const FbpDev &p, const FbpWs &w, hipStream_t s,
+                   KernelProf *prof = nullptr);
 
 int fbp_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,
-             float *image, uint8_t *mask, void *ws, size_t ws_bytes, hipStream_t s)
+             float *image, uint8_t *mask, void *ws, size_t ws_bytes, hipStream_t s,
+             KernelProf *prof = nullptr)
 {
     if (!hist_ok(hist) || !grid_ok(grid) || !fbp_ok(fbp) || !image) return HULL_EINVAL;
     const size_t need = fbp_ws_layout(fbp, grid, nullptr).bytes;
     if (!ws || ws_bytes < need) return HULL_ENOMEM;
     FbpWs w = fbp_ws_layout(fbp, grid, ws);
     const FbpDev p = fbp_dev(fbp);
-    fbp_bin_stage(hist, p, w, s);
-    fbp_reconstruct(grid, p, w, w.sum, w.cnt, 1.0 / 65536.0, image, mask, s);
+    fbp_bin_stage(hist, p, w, s, prof);
+    fbp_reconstruct(grid, p, w, w.sum, w.cnt, 1.0 / 65536.0, image, mask, s, prof);
     return launch_status();
 }
 
 // Zeroes the FDK bin sums and counts and bins the histories into them (WEPL
 // in 2^-16 mm).
-void fbp_bin_stage(const hullmi_histories *hist, const FbpDev &p, const FbpWs &w, hipStream_t s)
+void fbp_bin_stage(const hullmi_histories *hist, const FbpDev &p, const FbpWs &w, hipStream_t s,
+                   KernelProf *prof)
 {
+    auto mark = [&](int k) { if (prof) prof->begin(k, s); };
+    auto done = [&]() { if (prof) prof->end(s); };
     const int64_t nb = (int64_t)p.nu * p.nv * p.n_angles;
+    mark(HULL_PROF_FBP_CLEAR);
     fill_u64(w.sum, 0ull, nb, s);
     fill_u32(w.cnt, 0u, nb, s);
+    done();
+    mark(HULL_PROF_FBP_BIN);
     if (hist->n > 0) {
-        // one or two LDS copies of a detector plane (12 bytes per bin each);
-        // chunks so that every resident block gets one
+        // an LDS copy of one detector plane (12 bytes per bin); chunks so
+        // that every resident block gets one
         const size_t plane_lds = (size_t)p.nu * p.nv * 12;
         const DevProps dp = dev_props();
         const size_t lim = allow_max_lds(reinterpret_cast<const void *>(k_fbp_bin_lds), dp.max_lds);
-        const int nplanes = 2 * plane_lds <= lim ? 2 : (plane_lds <= lim ? 1 : 0);
-        if (nplanes > 0) {
-            const size_t lds = nplanes * plane_lds;
+        if (plane_lds <= lim) {
+            const size_t lds = plane_lds;
             int occ = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fbp_bin_lds, kFbpBinThreads,
                                                              lds) != hipSuccess || occ < 1)
@@ -542,11 +599,12 @@ void fbp_bin_stage(const hullmi_histories *hist, const FbpDev &p, const FbpWs &w
                                                    (hist->n + kFbpBinThreads - 1) / kFbpBinThreads);
             const int64_t chunk = (hist->n + want - 1) / want;
             k_fbp_bin_lds<<<(unsigned)((hist->n + chunk - 1) / chunk), kFbpBinThreads, lds, s>>>(
-                *hist, p, w.sum, w.cnt, chunk, nplanes);
+                *hist, p, w.sum, w.cnt, chunk);
         } else {
             k_fbp_bin<<<blocks_for(hist->n), kBlock, 0, s>>>(*hist, p, w.sum, w.cnt);
         }
     }
+    done();
 }
 
 bool bsc_ok(const hullmi_bsc_params *b)
@@ -781,7 +839,8 @@ int masks_from_counts(const hullmi_grid *g, const hullmi_params *p, const int32_
 int counts_accumulate(const hullmi_histories *h, const hullmi_grid *g, const hullmi_params *p,
                       int32_t *N, int32_t *M, hullmi_stats *stats, void *ws, hipStream_t s)
 {
-    return run_counts(h, g, p->wepl_low, p->wepl_high, N, M, HULL_ACCUMULATE, stats, ws, s, 0);
+    return run_counts(h, g, p->wepl_low, p->wepl_high, N, M, HULL_ACCUMULATE, stats, ws, s,
+                      CountOpts{});
 }
 
 void zero_counts(int32_t *N, int32_t *M, hullmi_stats *stats, int64_t V, hipStream_t s)
@@ -841,23 +900,22 @@ int job_check(const hullmi_job &j)
     }
 }
 
-int job_run(const hullmi_job &j, void *ws, size_t ws_bytes, hipStream_t s, int walk_blocks)
+int job_run(const hullmi_job &j, void *ws, size_t ws_bytes, hipStream_t s, const CountOpts &o)
 {
     const hullmi_params &p = j.params;
     switch (j.op) {
     case HULL_OP_SC:
         return sc_impl(&j.hist, &j.grid, p.wepl_low, j.N, j.sc_mask, j.flags, j.stats, ws, ws_bytes,
-                       s, walk_blocks);
+                       s, o);
     case HULL_OP_MSC:
         return msc_impl(&j.hist, &j.grid, p.wepl_low, p.msc_n_t, p.msc_mode, p.nbr, j.N,
-                        j.msc_mask, j.flags, j.stats, ws, ws_bytes, s, walk_blocks);
+                        j.msc_mask, j.flags, j.stats, ws, ws_bytes, s, o);
     case HULL_OP_SM:
         return sm_impl(&j.hist, &j.grid, p.wepl_high, p.sm_frac_num, p.sm_frac_den, p.sm_mode,
-                       p.sm_scope, p.nbr, j.M, j.sm_mask, j.flags, j.stats, ws, ws_bytes, s,
-                       walk_blocks);
+                       p.sm_scope, p.nbr, j.M, j.sm_mask, j.flags, j.stats, ws, ws_bytes, s, o);
     case HULL_OP_ALL:
         return all_impl(&j.hist, &j.grid, &p, j.N, j.M, j.sc_mask, j.msc_mask, j.sm_mask, j.flags,
-                        j.stats, ws, ws_bytes, s, walk_blocks);
+                        j.stats, ws, ws_bytes, s, o);
     case HULL_OP_FBP:
         return fbp_impl(&j.hist, &j.grid, &j.fbp, j.image, j.fbp_mask, ws, ws_bytes, s);
     case HULL_OP_FBP_CUT:
@@ -929,7 +987,8 @@ int hull_sc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_lo
             uint8_t *mask, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
             void *stream)
 {
-    return sc_impl(hist, grid, wepl_low, N, mask, flags, stats, ws, ws_bytes, as_stream(stream), 0);
+    return sc_impl(hist, grid, wepl_low, N, mask, flags, stats, ws, ws_bytes, as_stream(stream),
+                   CountOpts{});
 }
 
 int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t n_t,
@@ -937,7 +996,7 @@ int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_l
              void *ws, size_t ws_bytes, void *stream)
 {
     return msc_impl(hist, grid, wepl_low, n_t, mode, nbr, N, mask, flags, stats, ws, ws_bytes,
-                    as_stream(stream), 0);
+                    as_stream(stream), CountOpts{});
 }
 
 int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_high, int32_t frac_num,
@@ -945,7 +1004,7 @@ int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_hi
             uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
 {
     return sm_impl(hist, grid, wepl_high, frac_num, frac_den, mode, scope, nbr, M, mask, flags,
-                   stats, ws, ws_bytes, as_stream(stream), 0);
+                   stats, ws, ws_bytes, as_stream(stream), CountOpts{});
 }
 
 int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
@@ -953,7 +1012,59 @@ int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
              uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
 {
     return all_impl(hist, grid, p, N, M, sc_mask, msc_mask, sm_mask, flags, stats, ws, ws_bytes,
-                    as_stream(stream), 0);
+                    as_stream(stream), CountOpts{});
+}
+
+// Sums the recorded event pairs per kernel (after the stream has finished).
+static int prof_collect(const KernelProf &prof, float *ms, int32_t *launches)
+{
+    if (prof.failed) return HULL_EDEVICE;
+    for (int k = 0; k < HULL_PROF_KERNELS; ++k) {
+        ms[k] = 0.0f;
+        if (launches) launches[k] = 0;
+    }
+    for (const KernelProf::Mark &m : prof.marks) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, m.a, m.b) != hipSuccess) return HULL_EDEVICE;
+        ms[m.kernel] += t;
+        if (launches) ++launches[m.kernel];
+    }
+    return HULL_OK;
+}
+
+// Waits for the profiled call's work (unless its arguments were refused and
+// nothing was enqueued) and sums its event pairs.
+static int prof_finish(int rc, hipStream_t s, const KernelProf &prof, float *ms, int32_t *launches)
+{
+    if (rc == HULL_EINVAL || rc == HULL_ENOMEM) return rc;
+    const bool synced = hipStreamSynchronize(s) == hipSuccess;
+    if (rc != HULL_OK) return rc;
+    if (!synced) return HULL_EDEVICE;
+    return prof_collect(prof, ms, launches);
+}
+
+int hull_count_profile(const hullmi_histories *hist, const hullmi_grid *grid,
+                       const hullmi_params *p, int32_t *N, int32_t *M, uint32_t flags,
+                       hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream, float *ms,
+                       int32_t *launches)
+{
+    if (!ms) return HULL_EINVAL;
+    KernelProf prof;
+    CountOpts o;
+    o.prof = &prof;
+    const int rc = all_impl(hist, grid, p, N, M, nullptr, nullptr, nullptr, flags, stats, ws,
+                            ws_bytes, as_stream(stream), o);
+    return prof_finish(rc, as_stream(stream), prof, ms, launches);
+}
+
+int hull_fbp_profile(const hullmi_histories *hist, const hullmi_grid *grid,
+                     const hullmi_fbp_params *fbp, float *image, uint8_t *mask, void *ws,
+                     size_t ws_bytes, void *stream, float *ms, int32_t *launches)
+{
+    if (!ms) return HULL_EINVAL;
+    KernelProf prof;
+    const int rc = fbp_impl(hist, grid, fbp, image, mask, ws, ws_bytes, as_stream(stream), &prof);
+    return prof_finish(rc, as_stream(stream), prof, ms, launches);
 }
 
 int hull_fbp(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_fbp_params *fbp,

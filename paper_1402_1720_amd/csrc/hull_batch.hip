@@ -125,8 +125,12 @@ int enqueue(hullmi_plan *p, hipStream_t origin)
         if (hipStreamWaitEvent(s, p->fork, 0) != hipSuccess) return HULL_EDEVICE;
     for (size_t j = 0; j < p->jobs.size(); ++j) {
         const int s = p->job_stream[j];
-        const int rc = job_run(p->jobs[j], p->ws[s], p->ws_bytes[s], p->streams[s],
-                               p->tuning.walk_blocks);
+        CountOpts o;
+        o.walk_blocks = p->tuning.walk_blocks;
+        o.ranges_per_group = p->tuning.ranges_per_group;
+        o.length_classes = p->tuning.length_classes;
+        o.run_stride = p->tuning.run_stride;
+        const int rc = job_run(p->jobs[j], p->ws[s], p->ws_bytes[s], p->streams[s], o);
         if (rc != HULL_OK) return rc;
     }
     for (size_t s = 0; s < p->streams.size(); ++s) {
@@ -188,61 +192,140 @@ std::string shape_key(int device, const hullmi_job *jobs, int n)
 
 hullmi_tuning default_tuning(int n_jobs)
 {
-    hullmi_tuning t;
+    hullmi_tuning t{};
     t.streams = std::max(1, std::min(4, n_jobs));
     t.use_graph = 1;
-    t.walk_blocks = 0;
     return t;
 }
 
-// Mean time of `reps` launches after one untimed launch (which also captures).
+bool tuning_ok(const hullmi_tuning &t)
+{
+    return t.streams >= 1 && t.streams <= kMaxStreams && t.walk_blocks >= 0 &&
+           (t.use_graph == 0 || t.use_graph == 1) && t.ranges_per_group >= 0 &&
+           t.ranges_per_group <= 64 && t.length_classes >= 0 && t.length_classes <= 16 &&
+           t.run_stride >= 0 && t.run_stride <= 256;
+}
+
+// The byte ranges a job reads (its histories) and writes (the outputs its op
+// fills), for the check that the jobs of a plan do not race.
+void job_spans(const hullmi_job &j, int idx, std::vector<Span> &out)
+{
+    const uintptr_t n4 = 4 * (uintptr_t)j.hist.n;
+    const uintptr_t V = (uintptr_t)j.grid.nx * j.grid.ny * j.grid.nz;
+    auto add = [&](const void *p, uintptr_t bytes, bool w) {
+        if (p && bytes) out.push_back(Span{(uintptr_t)p, (uintptr_t)p + bytes, idx, w});
+    };
+    const float *in[8] = {j.hist.x_in, j.hist.y_in, j.hist.z_in, j.hist.x_out,
+                          j.hist.y_out, j.hist.z_out, j.hist.angle_deg, j.hist.wepl};
+    for (const float *p : in) add(p, n4, false);
+    const bool counting = j.op == HULL_OP_SC || j.op == HULL_OP_MSC || j.op == HULL_OP_SM ||
+                          j.op == HULL_OP_ALL;
+    if (j.op == HULL_OP_SC || j.op == HULL_OP_MSC || j.op == HULL_OP_ALL) add(j.N, 4 * V, true);
+    if (j.op == HULL_OP_SM || j.op == HULL_OP_ALL) add(j.M, 4 * V, true);
+    if (j.op == HULL_OP_SC || j.op == HULL_OP_ALL) add(j.sc_mask, V, true);
+    if (j.op == HULL_OP_MSC || j.op == HULL_OP_ALL) add(j.msc_mask, V, true);
+    if (j.op == HULL_OP_SM || j.op == HULL_OP_ALL) add(j.sm_mask, V, true);
+    if (counting) add(j.stats, sizeof(hullmi_stats), true);
+    if (j.op == HULL_OP_FBP || j.op == HULL_OP_FBP_CUT) {
+        add(j.image, 4 * V, true);
+        add(j.fbp_mask, V, true);
+    }
+    if (j.op == HULL_OP_SC_BINNED) {
+        add(j.bsc_mask, V, true);
+        add(j.bsc_stats, sizeof(hullmi_bsc_stats), true);
+    }
+}
+
+// Median time of five launches after one untimed launch (which also
+// captures): the median keeps one slow launch from deciding the choice.
 int time_tuning(const hullmi_job *jobs, int n, const hullmi_tuning &t, hipStream_t s, float *ms)
 {
+    constexpr int kReps = 5;
     hullmi_plan *p = nullptr;
     int rc = build_plan(jobs, n, t, &p);
     if (rc != HULL_OK) return rc;
-    hipEvent_t a = nullptr, b = nullptr;
-    rc = HULL_EDEVICE;
-    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
-        rc = launch(p, s);
-        const int reps = 3;
-        if (rc == HULL_OK && hipEventRecord(a, s) != hipSuccess) rc = HULL_EDEVICE;
-        for (int r = 0; r < reps && rc == HULL_OK; ++r) rc = launch(p, s);
-        if (rc == HULL_OK && hipEventRecord(b, s) != hipSuccess) rc = HULL_EDEVICE;
-        if (rc == HULL_OK && hipEventSynchronize(b) != hipSuccess) rc = HULL_EDEVICE;
-        float e = 0.0f;
-        if (rc == HULL_OK && hipEventElapsedTime(&e, a, b) != hipSuccess) rc = HULL_EDEVICE;
-        *ms = e / reps;
+    hipEvent_t ev[kReps + 1] = {};
+    rc = HULL_OK;
+    for (int r = 0; r <= kReps && rc == HULL_OK; ++r)
+        if (hipEventCreate(&ev[r]) != hipSuccess) rc = HULL_EDEVICE;
+    if (rc == HULL_OK) rc = launch(p, s);
+    for (int r = 0; r < kReps && rc == HULL_OK; ++r) {
+        if (hipEventRecord(ev[r], s) != hipSuccess) rc = HULL_EDEVICE;
+        if (rc == HULL_OK) rc = launch(p, s);
+    }
+    if (rc == HULL_OK && hipEventRecord(ev[kReps], s) != hipSuccess) rc = HULL_EDEVICE;
+    if (rc == HULL_OK && hipEventSynchronize(ev[kReps]) != hipSuccess) rc = HULL_EDEVICE;
+    float t_ms[kReps] = {};
+    for (int r = 0; r < kReps && rc == HULL_OK; ++r)
+        if (hipEventElapsedTime(&t_ms[r], ev[r], ev[r + 1]) != hipSuccess) rc = HULL_EDEVICE;
+    if (rc == HULL_OK) {
+        std::sort(t_ms, t_ms + kReps);
+        *ms = t_ms[kReps / 2];
     }
     (void)hipStreamSynchronize(s);
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     free_plan(p);
     return rc;
 }
 
+// Coordinate search over the launch choices, timed on the batch itself:
+// streams x graph first, then one knob of the counting pass at a time
+// (ranges per walk workgroup, the walk grid cap, length classes, run
+// stride), each kept only when it beats the best so far by more than 1%.
 int autotune(const hullmi_job *jobs, int n, hullmi_tuning *best)
 {
     *best = default_tuning(n);
     for (int j = 0; j < n; ++j)
         if (jobs[j].flags & HULL_ACCUMULATE) return HULL_OK;   // timing runs would add up
+    bool counting = false;
+    for (int j = 0; j < n; ++j)
+        counting |= jobs[j].op == HULL_OP_SC || jobs[j].op == HULL_OP_MSC ||
+                    jobs[j].op == HULL_OP_SM || jobs[j].op == HULL_OP_ALL;
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return HULL_EDEVICE;
     float best_ms = INFINITY;
     int rc = HULL_OK;
+    auto consider = [&](const hullmi_tuning &t, float margin) {
+        float ms = 0.0f;
+        rc = time_tuning(jobs, n, t, s, &ms);
+        if (rc == HULL_OK && ms < best_ms * margin) {
+            best_ms = ms;
+            *best = t;
+        }
+        return rc == HULL_OK;
+    };
     for (int streams : {1, 2, 4, 8}) {
         if (streams > 1 && streams > n) break;
         for (int graph : {0, 1}) {
-            hullmi_tuning t{streams, graph, 0};
-            float ms = 0.0f;
-            rc = time_tuning(jobs, n, t, s, &ms);
-            if (rc != HULL_OK) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                *best = t;
-            }
+            hullmi_tuning t{};
+            t.streams = streams;
+            t.use_graph = graph;
+            if (!consider(t, 1.0f)) break;
         }
         if (rc != HULL_OK) break;
+    }
+    if (rc == HULL_OK && counting) {
+        for (int v : {2, 4, 8}) {
+            hullmi_tuning t = *best;
+            t.ranges_per_group = v;
+            if (!consider(t, 0.99f)) break;
+        }
+        for (int v : {128, 256}) {
+            hullmi_tuning t = *best;
+            t.walk_blocks = v;
+            if (rc != HULL_OK || !consider(t, 0.99f)) break;
+        }
+        for (int v : {8}) {
+            hullmi_tuning t = *best;
+            t.length_classes = v;
+            if (rc != HULL_OK || !consider(t, 0.99f)) break;
+        }
+        for (int v : {4, 16, 64}) {
+            hullmi_tuning t = *best;
+            t.run_stride = v;
+            if (rc != HULL_OK || !consider(t, 0.99f)) break;
+        }
     }
     (void)hipStreamDestroy(s);
     return rc;
@@ -262,11 +345,14 @@ int hull_batch_plan(const hullmi_job *jobs, int n_jobs, const hullmi_tuning *tun
     *plan = nullptr;
     for (int j = 0; j < n_jobs; ++j)
         if (job_check(jobs[j]) != HULL_OK) return HULL_EINVAL;
+    // jobs may run concurrently on different streams: none may write what
+    // another reads or writes
+    std::vector<Span> spans;
+    for (int j = 0; j < n_jobs; ++j) job_spans(jobs[j], j, spans);
+    if (spans_conflict(spans)) return HULL_EINVAL;
     hullmi_tuning t;
     if (tuning) {
-        if (tuning->streams < 1 || tuning->streams > kMaxStreams || tuning->walk_blocks < 0 ||
-            (tuning->use_graph != 0 && tuning->use_graph != 1))
-            return HULL_EINVAL;
+        if (!tuning_ok(*tuning)) return HULL_EINVAL;
         t = *tuning;
     } else {
         int dev = 0;

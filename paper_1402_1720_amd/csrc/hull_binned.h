@@ -21,7 +21,6 @@ constexpr int kHistPerBlock = kBinThreads * kHistPerThread;
 constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic walk
 constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
 constexpr int kTileThreads = 1024;      // workgroup of the LDS walk
-constexpr int kMaxTileHalfwords = (160 * 1024 - 16) / 2;   // 16-bit counters, 160 KB of LDS
 constexpr int kItemsPerRange = 65535;   // a range holds at most this many items: each adds
                                         // at most 1 to a voxel, so a 16-bit counter holds it
 constexpr int kWorkPerItem = 16;        // fixed cost of an item in visit units (set-up)
@@ -57,10 +56,12 @@ struct BinWs {
     uint4 *item;            // [B * kMaxSlicesPerLine] per item: a tile item's packed
                             // endpoints, replaced by its packed slice-walk state; the
                             // history of an overflow item
-    uint32_t *partial;      // [max_slots][tile_words]
+    uint32_t *partial;      // [max_slots][slot_words]
     int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
     int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;
+    int slot_words;         // tile_words rounded up to a multiple of four
     int stride, gnx;        // tile row length in counters (padded), grid columns
+    int run_stride;         // runs of a sub-bin ordered by block modulo this
     int64_t B;
 };
 

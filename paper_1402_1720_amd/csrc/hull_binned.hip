@@ -42,19 +42,19 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
     return s;
 }
 
-// Column of block b in the per-block count rows: blocks ordered by b % 8,
-// then b / 8. Runs of one sub-bin that lie next to each other in the item
-// list then come from blocks 8 apart (8 x 8192 histories), so the 64 items of
-// a walk wave hold lines of several gantry angles instead of one, which made
-// the walk about 10% faster on the 200x200x32 scan (strides of 16 to 256 gave
-// the same). The order inside a sub-bin changes no count.
-constexpr int kRunStride = 8;
-__device__ __forceinline__ int blk_col(int b, int nblk)
+// Column of block b in the per-block count rows: blocks ordered by b % r,
+// then b / r (r = the run stride, 8 by default). Runs of one sub-bin that lie
+// next to each other in the item list then come from blocks r apart (r x 8192
+// histories), so the 64 items of a walk wave hold lines of several gantry
+// angles instead of one, which made the walk about 10% faster on the
+// 200x200x32 scan (strides of 16 to 256 gave the same). The order inside a
+// sub-bin changes no count.
+__device__ __forceinline__ int blk_col(int b, int nblk, int r)
 {
-    const int x = b % kRunStride;
+    const int x = b % r;
     int before = 0;
-    for (int i = 0; i < x; ++i) before += (nblk - i + kRunStride - 1) / kRunStride;
-    return before + b / kRunStride;
+    for (int i = 0; i < x; ++i) before += (nblk - i + r - 1) / r;
+    return before + b / r;
 }
 
 // Number of entries of the non-decreasing array a[lo..hi) that are <= x.
@@ -102,14 +102,19 @@ __device__ __forceinline__ void unpack_line(const uint4 r, int q[6])
 // counters: the low 16 bits in the second word, bit 16 in bits 22 and 23 of
 // the third); |Dy| and |Dx| (below 2^19 on a tile line), the signs of the x
 // and y steps and a flag for a slice the line does not meet.
+// Bit 24 of the third word marks a line whose d is never zero in the slice
+// (odd d, or no voxel corner on the projected line): the walk may take the
+// corner-free loop for it.
 constexpr uint32_t kStateEmpty = 1u << 21;
+constexpr uint32_t kStateNoCorner = 1u << 24;
 
-__device__ __forceinline__ uint4 pack_state(const SliceState &s)
+__device__ __forceinline__ uint4 pack_state(const SliceState &s, bool no_corner)
 {
     if (s.first < 0) return make_uint4(0u, 0u, kStateEmpty, 0u);
     return make_uint4((uint32_t)s.d, ((uint32_t)s.first & 0xffffu) | (uint32_t)s.last << 16,
                       (uint32_t)s.ay | (uint32_t)(s.sx < 0) << 19 | (uint32_t)(s.sy < 0) << 20 |
-                          ((uint32_t)s.first >> 16) << 22 | ((uint32_t)s.last >> 16) << 23,
+                          ((uint32_t)s.first >> 16) << 22 | ((uint32_t)s.last >> 16) << 23 |
+                          (no_corner ? kStateNoCorner : 0u),
                       (uint32_t)s.ax);
 }
 
@@ -252,7 +257,7 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
         w.meta[j] = meta;
     }
     __syncthreads();
-    const int col = blk_col((int)blockIdx.x, w.nblk);
+    const int col = blk_col((int)blockIdx.x, w.nblk, w.run_stride);
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
         w.blk[(int64_t)b * w.nblk + col] = lh[b];
     if (st) {
@@ -397,7 +402,7 @@ __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
 __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w)
 {
     __shared__ uint32_t cur[kMaxSubBins];
-    const int col = blk_col((int)blockIdx.x, w.nblk);
+    const int col = blk_col((int)blockIdx.x, w.nblk, w.run_stride);
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
         cur[b] = w.sub_start[b] + w.blk[(int64_t)b * w.nblk + col];
     __syncthreads();
@@ -466,8 +471,20 @@ __global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
         unpack_line(cur, q);
         SliceState st;
         slice_state_tile(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, w.stride, t % w.nz, st);
-        w.item[p] = pack_state(st);
+        const bool nc = (st.d & 1) || corner_free(q[0], q[1], q[3] - q[0], q[4] - q[1]);
+        w.item[p] = pack_state(st, nc);
     }
+}
+
+// The walk loops issue their ds_add_u32 from inline assembly, which the
+// compiler's wait counting does not see: a plain barrier after them could let
+// another wave read a counter before the last adds land. Every barrier that
+// follows the assembly loops goes through this, which waits for the wave's
+// outstanding LDS operations first.
+__device__ __forceinline__ void barrier_after_asm_lds()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __syncthreads();
 }
 
 // Persistent workgroups over the ranges; a range is cut at slice boundaries
@@ -477,9 +494,9 @@ __global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
 // one is walked.
 __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, int ny)
 {
-    extern __shared__ uint32_t lds[];   // tile (tile_words), then 2 control words
+    extern __shared__ uint32_t lds[];   // tile (slot_words), then 2 control words
     uint32_t *tile = lds;
-    uint32_t *seg = lds + w.tile_words;
+    uint32_t *seg = lds + w.slot_words;
     const int nranges = w.ctl[kCtlRanges];
     // LDS byte address of the tile (the low 32 bits of a local pointer)
     const uint32_t tile_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)tile;
@@ -492,7 +509,7 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
                 seg[0] = min(b, w.tile_start[t + 1]);
                 seg[1] = (uint32_t)slot_of(w, nranges, x);
             }
-            for (int i = threadIdx.x; i < w.tile_words; i += blockDim.x) tile[i] = 0;
+            for (int i = threadIdx.x; i < w.slot_words; i += blockDim.x) tile[i] = 0;
             __syncthreads();
             const uint32_t y = seg[0], slot = seg[1];
             // the next item's record (contiguous across the workgroup) is in
@@ -511,23 +528,19 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
                 const int32_t oy = (a.z >> 20) & 1u ? -2 * w.stride : 2 * w.stride;
                 const int32_t off = (int32_t)(tile_base + 2 * ((a.y & 0xffffu) | ((a.z >> 22) & 1u) << 16));
                 const int32_t last = (int32_t)(tile_base + 2 * ((a.y >> 16) | ((a.z >> 23) & 1u) << 16));
-                // lines of one wave mostly share their step directions: when
-                // every live lane's d is odd (no corner can be hit), the wave
-                // takes the shorter loop
-                if (__all(!live || (a.x & 1u))) {
-                    if (live) walk_slice_lds16_odd((int32_t)a.x, off, last, incx, incy, ox, oy, nx + ny);
+                // when no live lane's line can pass through a voxel corner
+                // (nearly every wave), the wave takes the shorter loop
+                if (__all(!live || (a.z & kStateNoCorner))) {
+                    if (live) walk_slice_lds16_nocorner((int32_t)a.x, off, last, incx, incy, ox, oy, nx + ny);
                 } else if (live) {
                     walk_slice_lds16((int32_t)a.x, off, last, incx, incy, ox, oy, nx + ny);
                 }
                 it += S;
             }
-            // the loop's LDS adds are issued from inline assembly, which the
-            // compiler's wait counting does not see: wait for them here, or a
-            // barrier could let another wave flush a word before they land
-            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            __syncthreads();
-            uint32_t *dst = w.partial + (int64_t)slot * w.tile_words;
-            for (int i = threadIdx.x; i < w.tile_words; i += blockDim.x) dst[i] = tile[i];
+            barrier_after_asm_lds();
+            uint4 *dst = reinterpret_cast<uint4 *>(w.partial + (int64_t)slot * w.slot_words);
+            const uint4 *src = reinterpret_cast<const uint4 *>(tile);
+            for (int i = threadIdx.x; i < w.slot_words / 4; i += blockDim.x) dst[i] = src[i];
             x = y;
             __syncthreads();
         }
@@ -535,7 +548,10 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
 }
 
 // Adds the partial slots of every slice into N or M; the sum of what is added
-// is the number of voxel visits of the class.
+// is the number of voxel visits of the class. A thread owns four consecutive
+// words (eight counters) of the tile and reads them from every slot of the
+// slice as one 16-byte load (slots are padded to a multiple of four words),
+// four slots in flight at a time.
 __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N, int *M, hullmi_stats *st)
 {
     __shared__ uint32_t slots[256];
@@ -546,8 +562,8 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N
     const uint32_t ta = w.tile_start[t], tb = w.tile_start[t + 1];
     if (ta == tb) return;   // uniform across the block
     const int nranges = w.ctl[kCtlRanges];
-    const int wd = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t lo = 0, hi = 0;
+    const int wd = 4 * (blockIdx.x * blockDim.x + threadIdx.x);   // first of four words
+    uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
     if (threadIdx.x == 0) r0 = count_le(w.range_start, 0, nranges + 1, ta) - 1;
     __syncthreads();
     // ranges overlapping [ta, tb), 256 at a time, one per thread: the ranges
@@ -563,42 +579,47 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N
         slots[threadIdx.x] = sl;
         const int n = __syncthreads_count(in);
         if (wd < w.tile_words) {
-            // eight slots' words in flight at a time
-            auto word = [&](int s) {
+            auto quad = [&](int s) {
                 const uint32_t q = slots[s];
-                return q == 0xffffffffu ? 0u : w.partial[(int64_t)q * w.tile_words + wd];
+                return q == 0xffffffffu
+                           ? make_uint4(0u, 0u, 0u, 0u)
+                           : *reinterpret_cast<const uint4 *>(w.partial + (int64_t)q * w.slot_words + wd);
+            };
+            auto add = [&](const uint4 v) {
+                lo[0] += v.x & 0xffffu; hi[0] += v.x >> 16;
+                lo[1] += v.y & 0xffffu; hi[1] += v.y >> 16;
+                lo[2] += v.z & 0xffffu; hi[2] += v.z >> 16;
+                lo[3] += v.w & 0xffffu; hi[3] += v.w >> 16;
             };
             int s = 0;
-            for (; s + 8 <= n; s += 8) {
-                uint32_t v[8];
+            for (; s + 4 <= n; s += 4) {
+                uint4 v[4];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = word(s + u);
+                for (int u = 0; u < 4; ++u) v[u] = quad(s + u);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    lo += v[u] & 0xffffu;
-                    hi += v[u] >> 16;
-                }
+                for (int u = 0; u < 4; ++u) add(v[u]);
             }
-            for (; s < n; ++s) {
-                const uint32_t v = word(s);
-                lo += v & 0xffffu;
-                hi += v >> 16;
-            }
+            for (; s < n; ++s) add(quad(s));
         }
         if (n < 256) break;   // uniform: n is the same in every thread
         __syncthreads();      // slots are rewritten in the next round
     }
     int *dst = cls ? M : N;
-    if (wd < w.tile_words) {
-        // counters 2 wd and 2 wd + 1 lie in one tile row (rows hold an even
-        // number of counters); those past column nx - 1 are padding
-        const int y = 2 * wd / w.stride, x = 2 * wd - y * w.stride;
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int wu = wd + u;
+        if (wu >= w.tile_words) break;
+        // counters 2 wu and 2 wu + 1 lie in one tile row (rows hold an even
+        // number of counters); those past column nx - 1 are padding and hold 0
+        const int y = 2 * wu / w.stride, x = 2 * wu - y * w.stride;
         const int64_t v0 = (int64_t)k * plane + (int64_t)y * w.gnx + x;
-        if (x < w.gnx) dst[v0] += (int)lo;
-        if (x + 1 < w.gnx) dst[v0 + 1] += (int)hi;
+        if (x < w.gnx) dst[v0] += (int)lo[u];
+        if (x + 1 < w.gnx) dst[v0 + 1] += (int)hi[u];
+        tot += (unsigned long long)lo[u] + hi[u];
     }
     if (st) {
-        const unsigned long long v = block_sum((unsigned long long)lo + hi, red);
+        const unsigned long long v = block_sum(tot, red);
         if (threadIdx.x == 0) add_stats(st, 4 + cls, v);
     }
 }

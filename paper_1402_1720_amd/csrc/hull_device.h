@@ -257,12 +257,15 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
         : "vcc", "scc", "memory");
 }
 
-// walk_slice_lds16 for lanes whose decision variable is odd. Both increments
-// of d are even, so an odd d stays odd and is never zero: the line never
-// passes through a voxel corner (its x and y steps go in opposite directions),
-// and each step is an x step (d < 0) or a y step. 9 VALU instructions per
-// step instead of 12; the same voxels.
-__device__ __forceinline__ void walk_slice_lds16_odd(int32_t d, int32_t off, int32_t last,
+// walk_slice_lds16 for lines whose decision variable is never zero in the
+// slice, so that each step is an x step (d < 0) or a y step (d > 0): 9 VALU
+// instructions per step instead of 12, the same voxels. d = 0 means that the
+// next x and y crossings coincide, i.e. the line passes through a voxel
+// corner with both indices moving the same way. That never happens when d is
+// odd (both increments of d are even, so an odd d stays odd: the x and y
+// steps go in opposite directions), nor when the projected line holds no
+// lattice corner at all (corner_free below).
+__device__ __forceinline__ void walk_slice_lds16_nocorner(int32_t d, int32_t off, int32_t last,
                                                      int32_t incx, int32_t incy, int32_t ox,
                                                      int32_t oy, int32_t maxit)
 {
@@ -294,6 +297,18 @@ __device__ __forceinline__ void walk_slice_lds16_odd(int32_t d, int32_t off, int
         : [last] "v"(last), [incx] "v"(incx), [incy] "v"(incy), [ox] "v"(ox), [oy] "v"(oy),
           [k16] "s"(65535)
         : "vcc", "scc", "memory");
+}
+
+// Whether the line's projection on the x-y plane passes through no voxel
+// corner (no point with both coordinates multiples of kQ): a corner
+// (kQ i, kQ j) on P + t D needs kQ (Dy i - Dx j) = Dy Px - Dx Py, so it
+// cannot exist when Dy Px - Dx Py is not a multiple of kQ. Only the low ten
+// bits of that product are needed, and 32-bit wrap-around keeps them.
+// Sufficient, not necessary: lines it cannot clear walk the general loop.
+__device__ __forceinline__ bool corner_free(int32_t px, int32_t py, int32_t dx, int32_t dy)
+{
+    const uint32_t c = (uint32_t)dy * (uint32_t)px - (uint32_t)dx * (uint32_t)py;
+    return (c & (uint32_t)(kQ - 1)) != 0u;
 }
 
 // Walk state of A_i inside z-slice k for walk_slice_lds16, set up once per

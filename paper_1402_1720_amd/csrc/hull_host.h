@@ -111,4 +111,27 @@ inline std::vector<int> assign_streams(const std::vector<double> &cost, int stre
     return out;
 }
 
+// A byte range [begin, end) that job `job` reads or writes.
+struct Span {
+    uintptr_t begin, end;
+    int job;
+    bool write;
+};
+
+// Whether ranges of two different jobs overlap where at least one of them is
+// written: such jobs race when they run on different streams. Ranges of one
+// job are not compared with each other; empty ranges never overlap.
+inline bool spans_conflict(std::vector<Span> v)
+{
+    std::sort(v.begin(), v.end(), [](const Span &a, const Span &b) { return a.begin < b.begin; });
+    for (size_t i = 0; i < v.size(); ++i) {
+        if (v[i].begin >= v[i].end) continue;
+        for (size_t j = i + 1; j < v.size() && v[j].begin < v[i].end; ++j) {
+            if (v[j].begin >= v[j].end || v[j].job == v[i].job) continue;
+            if (v[i].write || v[j].write) return true;
+        }
+    }
+    return false;
+}
+
 }  // namespace hullmi

@@ -98,7 +98,7 @@ __global__ void k_sm_edge_mask(const int *M, const long long *mt, uint8_t *mask,
 __global__ void k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt);
 constexpr int kFbpBinThreads = 1024;   // block of the LDS-binned FDK histogram
 __global__ void k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt,
-                              int64_t chunk, int nplanes);
+                              int64_t chunk);
 constexpr int kFbpFilterRows = 4;   // detector rows per filter block
 __global__ void k_fbp_filter(const unsigned long long *sum, const unsigned *cnt, float *q, FbpDev p,
                              double unit);

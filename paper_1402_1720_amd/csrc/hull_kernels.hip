@@ -246,28 +246,41 @@ k_fbp_bin(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt)
     atomicAdd(cnt + b, 1u);
 }
 
-// The same binning for a chunk of consecutive histories per block. Histories
-// arrive angle by angle, so the angle bins of a chunk's first and last history
-// usually hold all of it: each gets an LDS copy of the detector plane (sums and
-// counts, nplanes = 2, or only the first with nplanes = 1), added to the global
-// sums once; histories of any other angle bin go straight to the global sums.
-// The next history's fields are loaded while the current one is binned. Same
-// fixed point, so the sums are identical to k_fbp_bin's.
+// The same binning for a chunk of consecutive histories per block, through an
+// LDS copy of one detector plane (sums and counts). The plane follows the
+// histories' gantry angle: after every round of blockDim histories, when the
+// angle bin of the round's last history differs from the plane's, the plane
+// is added to the global sums and restarts on that angle. Histories come in
+// long runs of one angle, so nearly all of them land in LDS and each block
+// flushes its plane about once per angle it crosses; a history of any other
+// angle goes straight to the global sums (any order of histories gives the
+// same sums). The next history's fields are loaded while the current one is
+// binned. Same fixed point, so the sums are identical to k_fbp_bin's.
 __global__ void __launch_bounds__(kFbpBinThreads)
-k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt, int64_t chunk,
-              int nplanes)
+k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *cnt, int64_t chunk)
 {
-    extern __shared__ unsigned long long lsum[];   // nplanes plane sums, then nplanes plane counts
+    extern __shared__ unsigned long long lsum[];   // the plane's sums, then its counts
     const int plane = p.nu * p.nv;
-    unsigned *lcnt = reinterpret_cast<unsigned *>(lsum + (int64_t)nplanes * plane);
+    unsigned *lcnt = reinterpret_cast<unsigned *>(lsum + plane);
     const int64_t base = (int64_t)blockIdx.x * chunk;
     const int64_t end = min(base + chunk, h.n);
     if (base >= end) return;   // uniform across the block
-    for (int b = threadIdx.x; b < nplanes * plane; b += blockDim.x) { lsum[b] = 0ull; lcnt[b] = 0u; }
-    const int k0 = fbp_angle_bin(h.angle_deg[base], p);
-    int k1 = nplanes > 1 ? fbp_angle_bin(h.angle_deg[end - 1], p) : -1;
-    if (k1 == k0) k1 = -1;
+    for (int b = threadIdx.x; b < plane; b += blockDim.x) { lsum[b] = 0ull; lcnt[b] = 0u; }
+    int kcur = fbp_angle_bin(h.angle_deg[base], p);   // -1: no plane yet
     __syncthreads();
+    // adds the plane's non-empty bins to angle k's global sums and clears them
+    auto flush = [&](int k) {
+        for (int b = threadIdx.x; b < plane; b += blockDim.x) {
+            const unsigned c = lcnt[b];
+            if (c) {
+                const int64_t g = (int64_t)k * plane + b;
+                atomicAdd(sum + g, lsum[b]);
+                atomicAdd(cnt + g, c);
+                lsum[b] = 0ull;
+                lcnt[b] = 0u;
+            }
+        }
+    };
     struct F8 { float xi, yi, zi, xo, yo, zo, a, w; };
     auto fetch = [&](int64_t i, F8 &f) {
         if (i < end) {
@@ -278,34 +291,35 @@ k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *c
     };
     F8 nf{};
     fetch(base + threadIdx.x, nf);
-    for (int64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+    // every thread runs the same rounds: the plane switch needs the whole block
+    for (int64_t i0 = base; i0 < end; i0 += blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
         const F8 f = nf;
         fetch(i + blockDim.x, nf);
         int k, iu, iv;
         long long fx;
-        if (!fbp_locate_vals(f.xi, f.yi, f.zi, f.xo, f.yo, f.zo, f.a, f.w, p, k, iu, iv, fx))
-            continue;
-        const int pb = iv * p.nu + iu;
-        if (k == k0 || k == k1) {
-            const int lb = (k == k0 ? 0 : plane) + pb;
-            atomicAdd(&lsum[lb], (unsigned long long)fx);
-            atomicAdd(&lcnt[lb], 1u);
-        } else {
-            const int64_t b = (int64_t)k * plane + pb;
-            atomicAdd(sum + b, (unsigned long long)fx);
-            atomicAdd(cnt + b, 1u);
+        if (i < end && fbp_locate_vals(f.xi, f.yi, f.zi, f.xo, f.yo, f.zo, f.a, f.w, p, k, iu, iv, fx)) {
+            const int pb = iv * p.nu + iu;
+            if (k == kcur) {
+                atomicAdd(&lsum[pb], (unsigned long long)fx);
+                atomicAdd(&lcnt[pb], 1u);
+            } else {
+                const int64_t b = (int64_t)k * plane + pb;
+                atomicAdd(sum + b, (unsigned long long)fx);
+                atomicAdd(cnt + b, 1u);
+            }
+        }
+        // the same value in every thread: the round's last history
+        const int kn = fbp_angle_bin(h.angle_deg[min(i0 + (int64_t)blockDim.x, end) - 1], p);
+        if (kn >= 0 && kn != kcur) {
+            __syncthreads();
+            if (kcur >= 0) flush(kcur);
+            __syncthreads();
+            kcur = kn;
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nplanes * plane; b += blockDim.x) {
-        const int kb = b < plane ? k0 : k1;
-        const unsigned c = lcnt[b];
-        if (kb >= 0 && c) {
-            const int64_t g = (int64_t)kb * plane + (b < plane ? b : b - plane);
-            atomicAdd(sum + g, lsum[b]);
-            atomicAdd(cnt + g, c);
-        }
-    }
+    if (kcur >= 0) flush(kcur);
 }
 
 // One block per detector row: bin means (sums in fixed point of `unit` mm),

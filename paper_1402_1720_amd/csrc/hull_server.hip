@@ -154,14 +154,19 @@ int hullmi_server::process(const hullmi_request &r, char *mem, hipStream_t s, hi
         ok = hipMemcpyAsync(const_cast<float *>(c.in[a]), host_in[a], 4 * n,
                             hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipEventRecord(ev[1], s) == hipSuccess;
-    if (!ok) return HULL_EDEVICE;
+    if (!ok) {
+        // copies enqueued before the failure may still be writing into the
+        // block: wait for them before the block goes back to the arena
+        (void)hipStreamSynchronize(s);
+        return HULL_EDEVICE;
+    }
     j.hist.x_in = c.in[0]; j.hist.y_in = c.in[1]; j.hist.z_in = c.in[2];
     j.hist.x_out = c.in[3]; j.hist.y_out = c.in[4]; j.hist.z_out = c.in[5];
     j.hist.angle_deg = c.in[6]; j.hist.wepl = c.in[7];
     j.N = c.N; j.M = c.M; j.sc_mask = c.sc; j.msc_mask = c.msc; j.sm_mask = c.sm;
     j.image = c.image; j.fbp_mask = c.fmask; j.stats = c.stats;
     j.bsc_mask = c.bmask; j.bsc_stats = c.bstats;
-    const int rc = job_run(j, c.ws, c.ws_bytes, s, 0);
+    const int rc = job_run(j, c.ws, c.ws_bytes, s, CountOpts{});
     if (rc != HULL_OK) {
         (void)hipStreamSynchronize(s);
         return rc;

@@ -25,7 +25,7 @@ HULL_NBR_INPLANE4, HULL_NBR_SPATIAL6 = 0, 1
 (HULL_OP_SC, HULL_OP_MSC, HULL_OP_SM, HULL_OP_ALL, HULL_OP_FBP, HULL_OP_COUNT_LINES,
  HULL_OP_SC_BINNED, HULL_OP_FBP_CUT) = range(8)
 
-ABI_VERSION = 2          # the struct layouts below
+ABI_VERSION = 3          # the struct layouts below
 FIELDS = ("x_in", "y_in", "z_in", "x_out", "y_out", "z_out", "angle_deg", "wepl")
 
 
@@ -82,7 +82,11 @@ class hullmi_job(ctypes.Structure):
 
 class hullmi_tuning(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("walk_blocks", ctypes.c_int32)]
+                ("walk_blocks", ctypes.c_int32), ("ranges_per_group", ctypes.c_int32),
+                ("length_classes", ctypes.c_int32), ("run_stride", ctypes.c_int32)]
+
+    def as_dict(self) -> Dict[str, int]:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class hullmi_request(ctypes.Structure):
@@ -128,6 +132,8 @@ SIGNATURES = {
     "hull_fbp_cut": ([_P, _P, _P, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_count_lines": ([_P, _P, _I64, _P, _P, _U32, _P, _P, _SZ, _P], ctypes.c_int),
     "hull_quantize": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "hull_count_profile": ([_P, _P, _P, _P, _P, _U32, _P, _P, _SZ, _P, _P, _P], ctypes.c_int),
+    "hull_fbp_profile": ([_P, _P, _P, _P, _P, _P, _SZ, _P, _P, _P], ctypes.c_int),
     "hull_footprint_bytes": ([ctypes.c_int, _P, _I64, _P], _SZ),
     "hull_batch_plan": ([_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "hull_batch_launch": ([_P, _P], ctypes.c_int),
@@ -353,6 +359,62 @@ def hull_all(hist: Histories, grid, params: hullmi_params, N: torch.Tensor, M: t
                         _dev_ptr(sm_mask, torch.uint8, V, "sm_mask", d), int(flags),
                         _stats_ptr(stats), wp, wn, _stream(stream))
     _check(rc, "hull_all")
+
+
+# hull_prof_kernel entries: counting pass, then the FDK hull
+PROF_KERNELS = ("classify", "scan", "plan", "scatter", "setup", "walk", "reduce", "overflow",
+                "fbp_clear", "fbp_bin", "fbp_filter", "fbp_geometry", "fbp_backproject")
+PROF_KERNEL_NAMES = ("k_bin_classify", "k_bin_scan_blocks", "k_bin_plan", "k_bin_scatter",
+                     "k_item_setup", "k_walk_tiles", "k_reduce_tiles", "k_walk_overflow",
+                     "k_fill_u64 + k_fill_u32", "k_fbp_bin_lds", "k_fill_u32 + k_fbp_filter",
+                     "k_fbp_trig + k_fbp_footprint", "k_fbp_backproject_tiles")
+
+
+def _prof_result(ms, n, keys):
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(PROF_KERNELS) if k in keys}
+
+
+def hull_count_profile(hist: Histories, grid, params: hullmi_params, N: torch.Tensor,
+                       M: torch.Tensor, flags: int = 0, stats=None, ws=None, stream=None):
+    """The counting pass of hull_all with an event pair around every kernel
+    launch; waits for the stream and returns {kernel: (ms summed over its
+    launches, launches)}."""
+    g = make_grid(grid)
+    V = _voxels(g)
+    if ws is None:
+        ws = workspace(HULL_OP_ALL, g, hist.n, hist.device)
+    wp, wn = _ws(ws)
+    d = hist.device
+    K = len(PROF_KERNELS)
+    ms = (ctypes.c_float * K)()
+    n = (ctypes.c_int32 * K)()
+    rc = lib().hull_count_profile(ctypes.byref(hist.c), ctypes.byref(g), ctypes.byref(params),
+                                  _dev_ptr(N, torch.int32, V, "N", d),
+                                  _dev_ptr(M, torch.int32, V, "M", d), int(flags),
+                                  _stats_ptr(stats), wp, wn, _stream(stream), ms, n)
+    _check(rc, "hull_count_profile")
+    return _prof_result(ms, n, PROF_KERNELS[:8])
+
+
+def hull_fbp_profile(hist: Histories, grid, fbp: "hullmi_fbp_params", image: torch.Tensor,
+                     mask: Optional[torch.Tensor] = None, ws=None, stream=None):
+    """hull_fbp with an event pair around every kernel launch; waits for the
+    stream and returns {kernel: (ms summed over its launches, launches)}."""
+    g = make_grid(grid)
+    V = _voxels(g)
+    if ws is None:
+        ws = workspace(HULL_OP_FBP, g, hist.n, hist.device, fbp)
+    wp, wn = _ws(ws)
+    d = hist.device
+    K = len(PROF_KERNELS)
+    ms = (ctypes.c_float * K)()
+    n = (ctypes.c_int32 * K)()
+    rc = lib().hull_fbp_profile(ctypes.byref(hist.c), ctypes.byref(g), ctypes.byref(fbp),
+                                _dev_ptr(image, torch.float32, V, "image", d),
+                                _dev_ptr(mask, torch.uint8, V, "mask", d), wp, wn,
+                                _stream(stream), ms, n)
+    _check(rc, "hull_fbp_profile")
+    return _prof_result(ms, n, PROF_KERNELS[8:])
 
 
 def make_fbp_params(geo) -> hullmi_fbp_params:

@@ -1,5 +1,5 @@
-// Host-only checks of the batch/server building blocks (arena allocator and
-// stream assignment). Prints "ok" and exits 0, or names the first failure.
+// Host-only checks of the batch/server building blocks (arena allocator,
+// stream assignment and the race check of batch plans). Prints "ok" and exits 0, or names the first failure.
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -98,11 +98,44 @@ static void assign()
     CHECK(hullmi::assign_streams({}, 4).empty());
 }
 
+// The race check of batch plans: overlapping byte ranges of different jobs
+// where one is written, against a brute-force pairwise test on random spans.
+static void spans()
+{
+    using hullmi::Span;
+    CHECK(!hullmi::spans_conflict({}));
+    // reads may share memory, writes may not; touching ends do not overlap
+    CHECK(!hullmi::spans_conflict({{0, 100, 0, false}, {50, 150, 1, false}}));
+    CHECK(hullmi::spans_conflict({{0, 100, 0, false}, {99, 150, 1, true}}));
+    CHECK(!hullmi::spans_conflict({{0, 100, 0, true}, {100, 150, 1, true}}));
+    CHECK(!hullmi::spans_conflict({{0, 100, 0, true}, {50, 60, 0, true}}));   // one job
+    CHECK(!hullmi::spans_conflict({{0, 0, 0, true}, {0, 10, 1, true}}));      // empty
+    CHECK(hullmi::spans_conflict({{0, 1000, 0, true}, {10, 20, 1, false}, {5, 6, 2, false}}));
+    std::mt19937_64 rng(777);
+    for (int it = 0; it < 2000; ++it) {
+        std::vector<Span> v;
+        const int n = 1 + (int)(rng() % 12);
+        for (int i = 0; i < n; ++i) {
+            const uintptr_t b = rng() % 1000, len = rng() % 80;
+            v.push_back(Span{b, b + len, (int)(rng() % 4), (rng() % 3) == 0});
+        }
+        bool want = false;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                if (i != j && v[i].job != v[j].job && (v[i].write || v[j].write) &&
+                    v[i].begin < v[i].end && v[j].begin < v[j].end &&
+                    v[i].begin < v[j].end && v[j].begin < v[i].end)
+                    want = true;
+        CHECK(hullmi::spans_conflict(v) == want);
+    }
+}
+
 int main()
 {
     arena_basic();
     arena_random();
     assign();
+    spans();
     std::printf("ok\n");
     return 0;
 }

@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_version_and_strerror():
-    assert H.hull_abi_version() == H.ABI_VERSION == 2
+    assert H.hull_abi_version() == H.ABI_VERSION == 3
     assert H.hull_strerror(H.HULL_OK) == "ok"
     assert H.hull_strerror(H.HULL_EINVAL) == "invalid argument"
     assert H.hull_strerror(12345) == "unknown status"
@@ -154,13 +154,17 @@ def _bins(src=2000.0):
     return H.hullmi_fbp_params(src, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
 
 
-def _job(**kw):
+def _job(at=0, **kw):
+    """A job whose fake device pointers lie at their own addresses (`at`
+    selects a 16 MiB window), so that jobs made with different `at` values
+    share no memory."""
+    base = FAKE.value + at * (16 << 20)
     j = H.hullmi_job()
     j.op = H.HULL_OP_SC
-    j.hist = _hist()
+    j.hist = H.hullmi_histories(*[base + k * (1 << 20) for k in range(8)], 10)
     j.grid = _grid()
     j.params = H.make_params()
-    j.N = FAKE.value
+    j.N = base + 8 * (1 << 20)
     for k, v in kw.items():
         setattr(j, k, v)
     return j
@@ -171,7 +175,7 @@ def test_batch_plan_rejects_bad_jobs_before_touching_the_device():
     out = ctypes.c_void_p()
     assert L.hull_batch_plan(None, 1, None, ctypes.byref(out)) == H.HULL_EINVAL
     assert L.hull_batch_plan(None, -1, None, ctypes.byref(out)) == H.HULL_EINVAL
-    jobs = (H.hullmi_job * 2)(_job(), _job())
+    jobs = (H.hullmi_job * 2)(_job(0), _job(1))
     assert L.hull_batch_plan(jobs, 2, None, None) == H.HULL_EINVAL
     bad = [_job(N=None), _job(op=9), _job(op=H.HULL_OP_SM), _job(grid=_grid(nx=0)),
            _job(hist=_hist(null="wepl")), _job(op=H.HULL_OP_MSC, params=H.make_params(msc_n_t=0)),
@@ -186,16 +190,69 @@ def test_batch_plan_rejects_bad_jobs_before_touching_the_device():
            _job(op=H.HULL_OP_FBP_CUT, fbp=_bins(), image=FAKE.value,
                 bsc=H.make_bsc_params(cut_sigmas=65))]
     for b in bad:
-        arr = (H.hullmi_job * 2)(_job(), b)
+        arr = (H.hullmi_job * 2)(_job(1), b)
         assert L.hull_batch_plan(arr, 2, None, ctypes.byref(out)) == H.HULL_EINVAL
         assert out.value is None
     # bad tuning
     for t in (H.hullmi_tuning(0, 1, 0), H.hullmi_tuning(17, 1, 0), H.hullmi_tuning(2, 2, 0),
-              H.hullmi_tuning(2, 1, -1)):
+              H.hullmi_tuning(2, 1, -1), H.hullmi_tuning(2, 1, 0, -1), H.hullmi_tuning(2, 1, 0, 65),
+              H.hullmi_tuning(2, 1, 0, 2, 17), H.hullmi_tuning(2, 1, 0, 2, -1),
+              H.hullmi_tuning(2, 1, 0, 2, 8, 257), H.hullmi_tuning(2, 1, 0, 2, 8, -1)):
         assert L.hull_batch_plan(jobs, 2, ctypes.byref(t), ctypes.byref(out)) == H.HULL_EINVAL
     assert L.hull_batch_launch(None, None) == H.HULL_EINVAL
     assert L.hull_batch_tuning(None, None) == H.HULL_EINVAL
     assert L.hull_batch_destroy(None) == H.HULL_OK
+
+
+def test_profile_calls_reject_bad_arguments():
+    L = H.lib()
+    ms = (ctypes.c_float * 13)()
+    n = (ctypes.c_int32 * 13)()
+    p = H.make_params()
+    g = _grid()
+    f = _bins()
+    # no place for the timings; a bad grid; a missing output; a short workspace
+    assert L.hull_count_profile(ctypes.byref(_hist()), ctypes.byref(g), ctypes.byref(p), FAKE,
+                                FAKE, 0, None, FAKE, 1 << 30, None, None, n) == H.HULL_EINVAL
+    assert L.hull_count_profile(ctypes.byref(_hist()), ctypes.byref(_grid(nx=0)), ctypes.byref(p),
+                                FAKE, FAKE, 0, None, FAKE, 1 << 30, None, ms, n) == H.HULL_EINVAL
+    assert L.hull_count_profile(ctypes.byref(_hist()), ctypes.byref(g), ctypes.byref(p), FAKE,
+                                None, 0, None, FAKE, 1 << 30, None, ms, n) == H.HULL_EINVAL
+    assert L.hull_count_profile(ctypes.byref(_hist()), ctypes.byref(g), ctypes.byref(p), FAKE,
+                                FAKE, 0, None, FAKE, 16, None, ms, n) == H.HULL_ENOMEM
+    assert L.hull_fbp_profile(ctypes.byref(_hist()), ctypes.byref(g), ctypes.byref(f), FAKE, None,
+                              FAKE, 1 << 30, None, None, n) == H.HULL_EINVAL
+    assert L.hull_fbp_profile(ctypes.byref(_hist()), ctypes.byref(g), None, FAKE, None,
+                              FAKE, 1 << 30, None, ms, n) == H.HULL_EINVAL
+    assert L.hull_fbp_profile(ctypes.byref(_hist()), ctypes.byref(g), ctypes.byref(f), FAKE, None,
+                              FAKE, 16, None, ms, n) == H.HULL_ENOMEM
+
+
+def test_batch_plan_rejects_jobs_that_would_race():
+    """The jobs of a plan run on several streams: two jobs writing the same
+    counts (for example chunks of one scan accumulating into one volume), a
+    job writing another's histories, or overlapping masks or counters are
+    refused before anything touches the device. The byte-range check itself
+    is also covered host-side in tests/host/runtime_host_check.cpp."""
+    L = H.lib()
+    out = ctypes.c_void_p()
+    V = 8 * 8 * 4
+    a = _job(0)
+    racing = [
+        _job(1, N=a.N, flags=H.HULL_ACCUMULATE),               # the same N
+        _job(1, N=a.N + 4 * V - 4),                             # its last word
+        _job(1, N=a.hist.wepl),                                 # writes a's WEPL
+        _job(1, op=H.HULL_OP_ALL, M=a.N, N=FAKE.value + (40 << 20)),
+        _job(1, sc_mask=a.N + 100),                             # mask inside a's N
+    ]
+    for b in racing:
+        arr = (H.hullmi_job * 2)(a, b)
+        assert L.hull_batch_plan(arr, 2, None, ctypes.byref(out)) == H.HULL_EINVAL
+        assert out.value is None
+    # the same tuning is valid; only the overlap makes it fail
+    t = H.hullmi_tuning(2, 1, 0)
+    arr = (H.hullmi_job * 2)(a, _job(1, N=a.N))
+    assert L.hull_batch_plan(arr, 2, ctypes.byref(t), ctypes.byref(out)) == H.HULL_EINVAL
 
 
 def test_server_argument_checks():

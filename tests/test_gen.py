@@ -3,6 +3,7 @@ quadrature of nested ellipsoids, beam geometry and determinism."""
 import math
 
 import numpy as np
+import pytest
 
 import gen
 
@@ -38,9 +39,10 @@ def test_scan_wepl_of_a_centred_sphere():
     assert np.array_equal(h["wepl"], want.astype(np.float32)) or np.allclose(h["wepl"], want, atol=1e-5)
 
 
-def test_nested_ellipsoids_match_quadrature():
+@pytest.mark.parametrize("kind", ["inserts", "ventricles"])
+def test_nested_ellipsoids_match_quadrature(kind):
     g = gen.Grid((200, 200, 32), (1.0, 1.0, 3.0))
-    ph = gen.head_phantom(g, inserts=True)
+    ph = gen.head_phantom(g, inserts=kind == "inserts", ventricles=kind == "ventricles")
     spec = gen.ScanSpec(g, 400, 180, ph, seed=5)
     h = gen.generate(spec, with_true=True)
     for i in range(0, 400, 7):
@@ -103,3 +105,32 @@ def test_phantom_slice_area_near_paper():
     skull = gen.head_phantom(g)[0]
     area = math.pi * skull.semi[0] * skull.semi[1]
     assert abs(area - 15336) / 15336 < 0.01
+
+
+def test_ventricle_phantom_chords_in_closed_form():
+    """Lines parallel to x through the centre height of the ventricles: the
+    WEPL is a sum of axis-aligned chords, 2 a sqrt(1 - (y/b)^2 - (z/c)^2) per
+    ellipsoid weighted by its RSP step (skull 1.6, brain 1.04 - 1.6, each
+    ventricle 0.9 - 1.04). Checked against the generator's own chords and
+    against the RSP the phantom assigns to points: the ventricles' centres
+    hold 0.9, the brain between them 1.04, the skull 1.6."""
+    g = gen.Grid((200, 200, 32), (1.0, 1.0, 3.0))
+    ph = gen.head_phantom(g, ventricles=True)
+    assert len(ph) == 4
+    skull, brain, v1, v2 = ph
+    assert abs(v1.drho - (0.9 - 1.04)) < 1e-12 and v1.centre[0] == -v2.centre[0] > 0
+    y, z = v1.centre[1], v1.centre[2]
+
+    def closed(e):
+        r = 1 - ((y - e.centre[1]) / e.semi[1]) ** 2 - ((z - e.centre[2]) / e.semi[2]) ** 2
+        return 2 * e.semi[0] * math.sqrt(r) if r > 0 else 0.0
+
+    want = sum(e.drho * closed(e) for e in ph)
+    got = sum(e.drho * gen.chord(e, (-150.0, y, z), (1.0, 0.0, 0.0)) for e in ph)
+    assert abs(got - want) < 1e-9
+    # both ventricles lie on this line, fully inside the brain
+    assert closed(v1) > 0 and closed(v2) > 0
+    assert closed(brain) > 2 * (abs(v1.centre[0]) + v1.semi[0])
+    rsp = gen.phantom_rsp(ph, np.array([v1.centre, v2.centre, (0.0, y, z),
+                                        (0.0, brain.semi[1] + 1.0, 0.0)]))
+    assert np.allclose(rsp, [0.9, 0.9, 1.04, 1.6])

@@ -186,22 +186,61 @@ def test_autotuned_plan_is_cached_and_correct(batch_case):
     plan, keep = _plan(batch_case, None)
     t = plan.tuning
     assert 1 <= t.streams <= 16 and t.use_graph in (0, 1) and t.walk_blocks >= 0
+    assert 0 <= t.ranges_per_group <= 64 and 0 <= t.length_classes <= 16
+    assert 0 <= t.run_stride <= 256
     plan.launch()
     torch.cuda.synchronize()
     _same(batch_case, keep)
     plan2, keep2 = _plan(batch_case, None)         # same shapes: the cached choice
-    t2 = plan2.tuning
-    assert (t2.streams, t2.use_graph, t2.walk_blocks) == (t.streams, t.use_graph, t.walk_blocks)
+    assert plan2.tuning.as_dict() == t.as_dict()
     plan.close()
     plan2.close()
 
 
-def test_walk_grid_cap_changes_nothing(batch_case):
-    plan, keep = _plan(batch_case, H.hullmi_tuning(2, 1, 37))
+# every value the autotuner tries for a knob of the counting pass, and the
+# extremes the ABI allows: the counts and masks never change
+@pytest.mark.parametrize("knobs", [dict(walk_blocks=37), dict(walk_blocks=128),
+                                   dict(walk_blocks=256), dict(ranges_per_group=1),
+                                   dict(ranges_per_group=2), dict(ranges_per_group=4),
+                                   dict(ranges_per_group=8), dict(ranges_per_group=64),
+                                   dict(length_classes=1), dict(length_classes=8),
+                                   dict(run_stride=1), dict(run_stride=4), dict(run_stride=16),
+                                   dict(run_stride=64), dict(run_stride=256),
+                                   dict(walk_blocks=64, ranges_per_group=3, length_classes=5,
+                                        run_stride=3)])
+def test_launch_choices_change_nothing(batch_case, knobs):
+    t = H.hullmi_tuning(2, 1)
+    for k, v in knobs.items():
+        setattr(t, k, v)
+    plan, keep = _plan(batch_case, t)
+    assert plan.tuning.as_dict() == t.as_dict()
     plan.launch()
     torch.cuda.synchronize()
     _same(batch_case, keep)
     plan.close()
+
+
+def test_jobs_may_share_their_histories(batch_case):
+    """Two jobs reading one scan's histories with outputs of their own are a
+    valid plan (only writes may not overlap); both equal the scan alone."""
+    c = next(c for c in batch_case if c["op"] == H.HULL_OP_ALL and c["spec"].n_hist > 0)
+    keep, jobs = [], []
+    for _ in range(2):
+        outs = _outputs(c["op"], c["V"])
+        st = torch.zeros(6, dtype=torch.int64, device=DEV)
+        jobs.append(H.make_job(c["op"], c["hist"], c["grid"], c["params"], stats=st, **outs))
+        keep.append((outs, st))
+    plan = H.BatchPlan(jobs, keep=keep + [c["hist"]], tuning=H.hullmi_tuning(2, 0))
+    plan.launch()
+    torch.cuda.synchronize()
+    _same([c, c], keep)
+    plan.close()
+    # two chunks accumulating into one volume would race on it: refused
+    N = keep[0][0]["N"]
+    bad = [H.make_job(H.HULL_OP_SC, c["hist"].slice(a, b), c["grid"], c["params"],
+                      flags=H.HULL_ACCUMULATE, N=N) for a, b in ((0, 100), (100, 200))]
+    with pytest.raises(H.HullError):
+        H.BatchPlan(bad, tuning=H.hullmi_tuning(2, 0))
 
 
 def test_range_counters_at_their_cap():

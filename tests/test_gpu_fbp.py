@@ -70,9 +70,32 @@ def test_fbp_edge_histories():
     _check(img, mask, ref, rmask, geo.threshold)
 
 
+@pytest.mark.parametrize("order", ["shuffled", "angle pairs"])
+def test_fbp_histories_out_of_angle_order(order):
+    """The LDS plane follows the gantry angle of the histories it bins and
+    sends every other angle to the global sums: histories in random order
+    (almost all global, the plane switching every round) and histories whose
+    angle alternates between two values give the oracle's image too."""
+    spec = gen.config_spec(2, n_hist=1_000_000)
+    h = gen.generate(spec)
+    rng = np.random.default_rng(5)
+    if order == "shuffled":
+        perm = rng.permutation(spec.n_hist)
+    else:
+        half = spec.n_hist // 2
+        perm = np.empty(spec.n_hist, np.int64)
+        perm[0::2] = np.arange(half)
+        perm[1::2] = np.arange(half, spec.n_hist)
+    h = {k: v[perm] for k, v in h.items()}
+    geo = spec.fbp_geometry(du=1.0, dv=5.0)
+    img, mask, ref, rmask = _run(h, spec.grid, geo)
+    _check(img, mask, ref, rmask, geo.threshold)
+
+
 @pytest.mark.parametrize("du,dv,path", [
     (0.05, 0.5, "detector plane beyond the LDS: global binning; footprints beyond the stage"),
     (0.25, 1.0, "one LDS plane per block"),
+    (0.5, 2.5, "an LDS plane per block, two blocks per CU"),
 ])
 def test_fbp_fine_detectors_take_the_fallback_paths(du, dv, path):
     """Fine detector sampling pushes the binning and the backprojection onto
@@ -85,8 +108,10 @@ def test_fbp_fine_detectors_take_the_fallback_paths(du, dv, path):
     plane_bytes = geo.nu * geo.nv * 12
     if path.startswith("detector plane beyond"):
         assert plane_bytes > 160 * 1024
-    else:
+    elif path.startswith("one LDS plane"):
         assert 80 * 1024 < plane_bytes <= 160 * 1024
+    else:
+        assert plane_bytes <= 80 * 1024
     img, mask, ref, rmask = _run(h, g, geo)
     _check(img, mask, ref, rmask, geo.threshold)
 

@@ -11,7 +11,9 @@ that). Compared bit for bit: the full N and M volumes (the crossing counts of
 Sections 3.3 and 3.4), the counters, and every mask rule on those volumes —
 SC (Algorithm 1), MSC by count and by the neighbour difference of Algorithm 2
 (in-plane and 3-D neighbourhoods), SM by fraction of max M and by Algorithm
-3's steepest-slope threshold, per volume and per slice.
+3's steepest-slope threshold, per volume and per slice. The FDK hull of the
+same scan (the other half of the benchmark step, Section 3.1) is held to the
+FP64 oracle's image within 1e-4 of its largest magnitude.
 
 The oracle pass takes a few minutes on 16 host cores; progress lines go to
 the terminal (capture disabled) so that a quiet stretch never exceeds about
@@ -43,6 +45,7 @@ def test_config3_full_volume_bit_exact(capfd):
     G = oracle.grid_of(grid)
     say(f"{n} histories on {grid.n}: generating into device arrays and counting on the host")
     arr = {k: torch.empty(n, dtype=torch.float32, device=DEV) for k in gen.FIELDS}
+    host = {k: np.empty(n, np.float32) for k in gen.FIELDS}   # for the FDK oracle
     rN = np.zeros(V, np.int64)
     rM = np.zeros(V, np.int64)
     rst = dict.fromkeys(H.STATS_FIELDS, 0)
@@ -52,6 +55,7 @@ def test_config3_full_volume_bit_exact(capfd):
         h = gen.generate(spec, h0, h1)
         for k in gen.FIELDS:
             arr[k][h0:h1].copy_(torch.from_numpy(h[k]))
+            host[k][h0:h1] = h[k]
         cN, cM, cst = oracle.counts(h, G)
         rN += cN
         rM += cM
@@ -107,3 +111,21 @@ def test_config3_full_volume_bit_exact(capfd):
         got = mask.cpu().numpy()
         assert np.array_equal(got, ref), (rule, mode, a, nbr, int((got != ref).sum()))
         say(f"{rule} mode {mode} ({a}, nbr {nbr}) bit-exact, {int(ref.sum())} voxels kept")
+
+    # the FDK hull of the full scan: FP32 image within 1e-4 of the FP64 oracle
+    geo = spec.fbp_geometry(du=1.0, dv=5.0)
+    fbp = H.make_fbp_params(geo)
+    img = torch.zeros(V, dtype=torch.float32, device=DEV)
+    fmask = torch.zeros(V, dtype=torch.uint8, device=DEV)
+    H.hull_fbp(hist, grid, fbp, img, fmask)
+    torch.cuda.synchronize()
+    say("FDK hull on the device done; oracle FDK (FP64)")
+    ref, rmask, _, _ = oracle.fbp(host, G, oracle.fbp_params(geo))
+    got = img.cpu().numpy().astype(np.float64)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale
+    assert err <= 1e-4, err
+    near = np.abs(ref - geo.threshold) <= 1e-4 * scale
+    gm = fmask.cpu().numpy()
+    assert np.array_equal(gm[~near], rmask[~near])
+    say(f"FDK image within {err:.1e} of the oracle's largest value, masks equal")
