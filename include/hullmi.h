@@ -319,6 +319,23 @@ int hull_fbp_profile(const hullmi_histories *hist, const hullmi_grid *grid,
                      const hullmi_fbp_params *fbp, float *image, uint8_t *mask, void *ws,
                      size_t ws_bytes, void *stream, float *ms, int32_t *launches);
 
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): hull_fbp with its workspace in a fixed device array of the
+ * library, HULLMI_NOALLOC_SCRATCH_BYTES long. Each device that runs the
+ * library holds its own copy until the process ends (set up on the first
+ * call on that device). The call allocates nothing; arguments, outputs and
+ * results are those of hull_fbp. HULL_EINVAL also when the geometry's
+ * workspace (hull_workspace_bytes(HULL_OP_FBP, ...)) exceeds the array, and
+ * HULL_EDEVICE when the array's address cannot be found. Every call on one
+ * device shares that device's array: calls that overlap in time on one
+ * device (other streams, other host threads) race and must be serialised by
+ * the caller; calls in sequence on one stream are safe (each call clears what
+ * it accumulates before using it). */
+#define HULLMI_NOALLOC_SCRATCH_BYTES (256u << 20)
+int hull_fbp_noalloc(const hullmi_histories *hist, const hullmi_grid *grid,
+                     const hullmi_fbp_params *fbp, float *image, uint8_t *mask, void *stream);
+
 /* The geometry step alone: per history status (0 ok, 1 non-finite field,
  * 2 endpoint out of range, 3 degenerate) and the quantised endpoints [n][3]
  * (int32, 1/1024 voxel; left unwritten for status 1 and 2). */

@@ -134,6 +134,7 @@ SIGNATURES = {
     "hull_quantize": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "hull_count_profile": ([_P, _P, _P, _P, _P, _U32, _P, _P, _SZ, _P, _P, _P], ctypes.c_int),
     "hull_fbp_profile": ([_P, _P, _P, _P, _P, _P, _SZ, _P, _P, _P], ctypes.c_int),
+    "hull_fbp_noalloc": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "hull_footprint_bytes": ([ctypes.c_int, _P, _I64, _P], _SZ),
     "hull_batch_plan": ([_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "hull_batch_launch": ([_P, _P], ctypes.c_int),
@@ -436,6 +437,22 @@ def hull_fbp(hist: Histories, grid, fbp: hullmi_fbp_params, image: torch.Tensor,
                         _dev_ptr(image, torch.float32, V, "image", d),
                         _dev_ptr(mask, torch.uint8, V, "mask", d), wp, wn, _stream(stream))
     _check(rc, "hull_fbp")
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20   # HULLMI_NOALLOC_SCRATCH_BYTES
+
+
+def hull_fbp_noalloc(hist: Histories, grid, fbp: hullmi_fbp_params, image: torch.Tensor,
+                     mask: Optional[torch.Tensor] = None, stream=None):
+    """hull_fbp with its workspace in the library's fixed device array (no
+    allocation in the call; calls overlapping on one device race)."""
+    g = make_grid(grid)
+    V = _voxels(g)
+    d = hist.device
+    rc = lib().hull_fbp_noalloc(ctypes.byref(hist.c), ctypes.byref(g), ctypes.byref(fbp),
+                                _dev_ptr(image, torch.float32, V, "image", d),
+                                _dev_ptr(mask, torch.uint8, V, "mask", d), _stream(stream))
+    _check(rc, "hull_fbp_noalloc")
 
 
 def hull_fbp_cut(hist: Histories, grid, fbp: hullmi_fbp_params, cut_sigmas: int,

@@ -228,6 +228,26 @@ def test_profile_calls_reject_bad_arguments():
                               FAKE, 16, None, ms, n) == H.HULL_ENOMEM
 
 
+def test_noalloc_fbp_rejects_bad_arguments_and_oversized_geometry():
+    """hull_fbp_noalloc checks its arguments as hull_fbp does, and refuses a
+    detector whose workspace exceeds the library's fixed array, before it
+    touches the device."""
+    L = H.lib()
+    g = _grid()
+    f = _bins()
+    assert L.hull_fbp_noalloc(None, ctypes.byref(g), ctypes.byref(f), FAKE, None, None) == H.HULL_EINVAL
+    assert L.hull_fbp_noalloc(ctypes.byref(_hist()), ctypes.byref(g), ctypes.byref(f), None, None,
+                              None) == H.HULL_EINVAL
+    assert L.hull_fbp_noalloc(ctypes.byref(_hist()), ctypes.byref(_grid(nx=0)), ctypes.byref(f),
+                              FAKE, None, None) == H.HULL_EINVAL
+    assert L.hull_fbp_noalloc(ctypes.byref(_hist()), ctypes.byref(g), None, FAKE, None,
+                              None) == H.HULL_EINVAL
+    big = H.hullmi_fbp_params(2000.0, 0.1, 0.1, -100.0, -50.0, 2000, 1000, 360, 0.0, 1.0, 0, 0.6)
+    assert H.hull_workspace_bytes(H.HULL_OP_FBP, g, 10, big) > H.NOALLOC_SCRATCH_BYTES
+    assert L.hull_fbp_noalloc(ctypes.byref(_hist()), ctypes.byref(g), ctypes.byref(big), FAKE,
+                              None, None) == H.HULL_EINVAL
+
+
 def test_batch_plan_rejects_jobs_that_would_race():
     """The jobs of a plan run on several streams: two jobs writing the same
     counts (for example chunks of one scan accumulating into one volume), a
