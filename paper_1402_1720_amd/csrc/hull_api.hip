@@ -149,23 +149,25 @@ size_t allow_max_lds(const void *fn, size_t max_lds)
 
 inline int64_t plane_of(const hullmi_grid *g) { return (int64_t)g->nx * g->ny; }
 
-// Counters per tile row: nx rounded up to even, plus 2 when half of that is
-// even, so that a row holds an odd number of LDS words and neighbouring rows
-// start in different banks; not padded when that would cost the second walk
-// workgroup on a CU.
+// Counters per tile row: odd (the walk loops rely on an x step and a y step
+// both moving to the other half of a 32-bit word), nx or nx + 1; two more
+// when a row would be a whole multiple of 64 words plus a half, where the
+// rows a walk wave adds into at the same step would share LDS banks; not
+// widened by those two when that would cost the second walk workgroup on a
+// CU.
 // LDS bytes of a walk workgroup for tile rows of `stride` counters: the tile
 // rounded up to whole 16-byte quads (the flush and the reduce move four words
 // at a time), then the control words.
 inline int64_t tile_lds_bytes(int64_t stride, int ny)
 {
-    return ((stride * ny / 2 + 3) & ~int64_t(3)) * 4 + 16;
+    return (((stride * ny + 1) / 2 + 3) & ~int64_t(3)) * 4 + 16;
 }
 inline int tile_stride(const hullmi_grid *g)
 {
-    const int e = (g->nx + 1) & ~1;
-    const int s = (e / 2) % 2 ? e : e + 2;
-    const int64_t two = 2 * tile_lds_bytes(s, g->ny), two_e = 2 * tile_lds_bytes(e, g->ny);
-    return two <= 160 * 1024 || two_e > 160 * 1024 ? s : e;
+    const int o = g->nx | 1;
+    const int s = (o / 2) % 64 == 0 ? o + 2 : o;
+    const int64_t two = 2 * tile_lds_bytes(s, g->ny), two_o = 2 * tile_lds_bytes(o, g->ny);
+    return two <= 160 * 1024 || two_o > 160 * 1024 ? s : o;
 }
 // A slice fits the LDS tile when its 16-bit counters, padded rows included,
 // fit the 160 KB of LDS.
@@ -213,8 +215,9 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.nblk = (int)((B + kHistPerBlock - 1) / kHistPerBlock);
     w.stride = tile_stride(g);
     w.gnx = g->nx;
+    w.gny = g->ny;
     w.run_stride = kDefaultRunStride;
-    w.tile_words = tile_fits(g) ? (int)((int64_t)w.stride * g->ny / 2) : 1;
+    w.tile_words = tile_fits(g) ? (int)(((int64_t)w.stride * g->ny + 1) / 2) : 1;
     w.slot_words = (w.tile_words + 3) & ~3;
     w.min_ranges = kMaxWalkGroups * kRangesPerGroup;
     // ranges: P0 = max(min_ranges, ceil(I / kItemsPerRange)) coarse ranges,

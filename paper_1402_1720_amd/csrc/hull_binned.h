@@ -60,7 +60,7 @@ struct BinWs {
     int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
     int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;
     int slot_words;         // tile_words rounded up to a multiple of four
-    int stride, gnx;        // tile row length in counters (padded), grid columns
+    int stride, gnx, gny;   // tile row length in counters (odd), grid columns and rows
     int run_stride;         // runs of a sub-bin ordered by block modulo this
     int64_t B;
 };

@@ -530,10 +530,14 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
                 const int32_t last = (int32_t)(tile_base + 2 * ((a.y >> 16) | ((a.z >> 23) & 1u) << 16));
                 // when no live lane's line can pass through a voxel corner
                 // (nearly every wave), the wave takes the shorter loop
+                // the first step adds to the half of the first counter's word
+                const uint32_t val = (off & 2) ? 65536u : 1u;
                 if (__all(!live || (a.z & kStateNoCorner))) {
-                    if (live) walk_slice_lds16_nocorner((int32_t)a.x, off, last, incx, incy, ox, oy, nx + ny);
+                    if (live)
+                        walk_slice_lds16_nocorner((int32_t)a.x, off, last, incx, incy, ox, oy, val,
+                                                  nx + ny);
                 } else if (live) {
-                    walk_slice_lds16((int32_t)a.x, off, last, incx, incy, ox, oy, nx + ny);
+                    walk_slice_lds16((int32_t)a.x, off, last, incx, incy, ox, oy, val, nx + ny);
                 }
                 it += S;
             }
@@ -606,16 +610,19 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(BinWs w, int plane, int *N
     }
     int *dst = cls ? M : N;
     unsigned long long tot = 0;
+    // counter c of the tile is voxel (c mod S, c / S) of the slice (S = the
+    // row length, odd); counters past column nx - 1 and past the last row are
+    // padding and hold 0
+    auto put = [&](int c, uint32_t v) {
+        const int y = c / w.stride, x = c - y * w.stride;
+        if (x < w.gnx && y < w.gny) dst[(int64_t)k * plane + (int64_t)y * w.gnx + x] += (int)v;
+    };
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int wu = wd + u;
         if (wu >= w.tile_words) break;
-        // counters 2 wu and 2 wu + 1 lie in one tile row (rows hold an even
-        // number of counters); those past column nx - 1 are padding and hold 0
-        const int y = 2 * wu / w.stride, x = 2 * wu - y * w.stride;
-        const int64_t v0 = (int64_t)k * plane + (int64_t)y * w.gnx + x;
-        if (x < w.gnx) dst[v0] += (int)lo[u];
-        if (x + 1 < w.gnx) dst[v0 + 1] += (int)hi[u];
+        put(2 * wu, lo[u]);
+        put(2 * wu + 1, hi[u]);
         tot += (unsigned long long)lo[u] + hi[u];
     }
     if (st) {

@@ -210,18 +210,26 @@ namespace hullmi {
 // the same way; mixed directions never tie, the sigma term breaks it), and
 // every step changes d by incx, incy or both.
 //
-// The loop is written directly in gfx950 assembly (the compiler keeps the loop
-// guard and the any-lane test in vector registers; here they are scalar): per
-// step 12 VALU instructions and one ds_add_u32 into the 16-bit LDS tile. Lanes
-// leave the exec mask when they have visited `last`; the loop also ends after
-// maxit rounds. Only LDS is touched: `off` and `last` are LDS byte addresses
-// of 16-bit counters (tile base + 2 * voxel, the base a multiple of 4), so the
-// word is off & ~3 and the half is bit 1 of off.
+// The loops are written directly in gfx950 assembly (the compiler keeps the
+// loop guard and the any-lane test in vector registers; here they are
+// scalar). Counters are 16 bits, two to an LDS word, in tile rows of an odd
+// number S of counters: the counter of voxel (x, y) is number L = x + S y, so
+// an x step (L +- 1) and a y step (L +- S) both move to the other half of a
+// word, and a corner step (both) stays in the same half. The value a step
+// adds to its word (1 or 65536) therefore alternates with every step that is
+// not a corner step. Lanes leave the exec mask when they have visited `last`;
+// the loop also ends after maxit rounds. Only LDS is touched: `off` and `last`
+// are LDS byte addresses of 16-bit counters (tile base + 2 L, the base a
+// multiple of 4), so the word is off & ~3; `val` is what the first step adds
+// (65536 when bit 1 of off is set, else 1).
+//
+// General loop: 12 VALU instructions and one ds_add_u32 per step.
 __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t last,
                                                  int32_t incx, int32_t incy, int32_t ox,
-                                                 int32_t oy, int32_t maxit)
+                                                 int32_t oy, uint32_t val, int32_t maxit)
 {
     const int32_t incxy = incx + incy, oxy = ox + oy;
+    const uint32_t flip = 65537u;
     int32_t t0, t1, t2;
     uint64_t save, sbx, stie;
     int32_t it = maxit;
@@ -234,15 +242,16 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
         "v_cmp_eq_u32 %[stie], 0, %[d]\n"
         "v_cmp_ne_u32 vcc, %[off], %[last]\n"
         "v_and_b32 %[t0], -4, %[off]\n"
-        "v_bfe_u32 %[t1], %[off], 1, 1\n"
         "v_cndmask_b32 %[t2], %[incy], %[incxy], %[stie]\n"
         "v_cndmask_b32 %[t2], %[t2], %[incx], %[sbx]\n"
         "v_add_u32 %[d], %[d], %[t2]\n"
-        "v_mad_u32_u24 %[t1], %[t1], %[k16], 1\n"
-        "ds_add_u32 %[t0], %[t1]\n"
+        "ds_add_u32 %[t0], %[val]\n"
+        // the next step adds to the other half unless this was a corner step
+        "v_cndmask_b32 %[t1], %[flip], 0, %[stie]\n"
         "v_cndmask_b32 %[t2], %[oy], %[oxy], %[stie]\n"
         "v_cndmask_b32 %[t2], %[t2], %[ox], %[sbx]\n"
         "v_add_u32 %[off], %[off], %[t2]\n"
+        "v_xor_b32 %[val], %[val], %[t1]\n"
         "s_and_b64 exec, exec, vcc\n"
         "s_cbranch_execz 2f\n"
         "s_sub_u32 %[it], %[it], 1\n"
@@ -250,42 +259,54 @@ __device__ __forceinline__ void walk_slice_lds16(int32_t d, int32_t off, int32_t
         "s_cbranch_scc0 1b\n"
         "2:\n"
         "s_mov_b64 exec, %[save]\n"
-        : [d] "+v"(d), [off] "+v"(off), [it] "+s"(it), [t0] "=&v"(t0), [t1] "=&v"(t1),
-          [t2] "=&v"(t2), [save] "=&s"(save), [sbx] "=&s"(sbx), [stie] "=&s"(stie)
+        : [d] "+v"(d), [off] "+v"(off), [val] "+v"(val), [it] "+s"(it), [t0] "=&v"(t0),
+          [t1] "=&v"(t1), [t2] "=&v"(t2), [save] "=&s"(save), [sbx] "=&s"(sbx),
+          [stie] "=&s"(stie)
         : [last] "v"(last), [incx] "v"(incx), [incy] "v"(incy), [incxy] "v"(incxy),
-          [ox] "v"(ox), [oy] "v"(oy), [oxy] "v"(oxy), [k16] "s"(65535)
+          [ox] "v"(ox), [oy] "v"(oy), [oxy] "v"(oxy), [flip] "v"(flip)
         : "vcc", "scc", "memory");
 }
 
 // walk_slice_lds16 for lines whose decision variable is never zero in the
-// slice, so that each step is an x step (d < 0) or a y step (d > 0): 9 VALU
-// instructions per step instead of 12, the same voxels. d = 0 means that the
-// next x and y crossings coincide, i.e. the line passes through a voxel
-// corner with both indices moving the same way. That never happens when d is
-// odd (both increments of d are even, so an odd d stays odd: the x and y
-// steps go in opposite directions), nor when the projected line holds no
-// lattice corner at all (corner_free below).
+// slice, so that each step is an x step (d < 0) or a y step (d > 0) and the
+// added value alternates at every step: two steps per round, the first
+// adding `val`, the second val ^ 65537, each step 7 VALU instructions and one
+// ds_add_u32; the same voxels. d = 0 means that the next x and y crossings
+// coincide, i.e. the line passes through a voxel corner with both indices
+// moving the same way. That never happens when d is odd (both increments of d
+// are even, so an odd d stays odd: the x and y steps go in opposite
+// directions), nor when the projected line holds no lattice corner at all
+// (corner_free below). maxit bounds the steps (rounds of two).
 __device__ __forceinline__ void walk_slice_lds16_nocorner(int32_t d, int32_t off, int32_t last,
-                                                     int32_t incx, int32_t incy, int32_t ox,
-                                                     int32_t oy, int32_t maxit)
+                                                          int32_t incx, int32_t incy, int32_t ox,
+                                                          int32_t oy, uint32_t val, int32_t maxit)
 {
+    const uint32_t val2 = val ^ 65537u;
     int32_t t0, t1, t2;
-    uint64_t save, sbx;
-    int32_t it = maxit;
+    uint64_t save, sbx, sdone;
+    int32_t it = (maxit + 1) >> 1;
     asm volatile(
         "s_mov_b64 %[save], exec\n"
         "1:\n"
         "v_cmp_gt_i32 %[sbx], 0, %[d]\n"
-        "v_cmp_ne_u32 vcc, %[off], %[last]\n"
+        "v_cmp_ne_u32 %[sdone], %[off], %[last]\n"
         "v_and_b32 %[t0], -4, %[off]\n"
-        "v_bfe_u32 %[t1], %[off], 1, 1\n"
         "v_cndmask_b32 %[t2], %[incy], %[incx], %[sbx]\n"
         "v_add_u32 %[d], %[d], %[t2]\n"
-        "v_mad_u32_u24 %[t1], %[t1], %[k16], 1\n"
-        "ds_add_u32 %[t0], %[t1]\n"
+        "ds_add_u32 %[t0], %[val]\n"
         "v_cndmask_b32 %[t2], %[oy], %[ox], %[sbx]\n"
         "v_add_u32 %[off], %[off], %[t2]\n"
-        "s_and_b64 exec, exec, vcc\n"
+        "s_and_b64 exec, exec, %[sdone]\n"
+        "s_cbranch_execz 2f\n"
+        "v_cmp_gt_i32 %[sbx], 0, %[d]\n"
+        "v_cmp_ne_u32 %[sdone], %[off], %[last]\n"
+        "v_and_b32 %[t1], -4, %[off]\n"
+        "v_cndmask_b32 %[t2], %[incy], %[incx], %[sbx]\n"
+        "v_add_u32 %[d], %[d], %[t2]\n"
+        "ds_add_u32 %[t1], %[val2]\n"
+        "v_cndmask_b32 %[t2], %[oy], %[ox], %[sbx]\n"
+        "v_add_u32 %[off], %[off], %[t2]\n"
+        "s_and_b64 exec, exec, %[sdone]\n"
         "s_cbranch_execz 2f\n"
         "s_sub_u32 %[it], %[it], 1\n"
         "s_cmp_eq_u32 %[it], 0\n"
@@ -293,10 +314,10 @@ __device__ __forceinline__ void walk_slice_lds16_nocorner(int32_t d, int32_t off
         "2:\n"
         "s_mov_b64 exec, %[save]\n"
         : [d] "+v"(d), [off] "+v"(off), [it] "+s"(it), [t0] "=&v"(t0), [t1] "=&v"(t1),
-          [t2] "=&v"(t2), [save] "=&s"(save), [sbx] "=&s"(sbx)
+          [t2] "=&v"(t2), [save] "=&s"(save), [sbx] "=&s"(sbx), [sdone] "=&s"(sdone)
         : [last] "v"(last), [incx] "v"(incx), [incy] "v"(incy), [ox] "v"(ox), [oy] "v"(oy),
-          [k16] "s"(65535)
-        : "vcc", "scc", "memory");
+          [val] "v"(val), [val2] "v"(val2)
+        : "scc", "memory");
 }
 
 // Whether the line's projection on the x-y plane passes through no voxel
