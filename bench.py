@@ -440,7 +440,7 @@ def config2(torch, gen, H, dev, args):
                          "achieved": bsc_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": bsc_gbs / PEAK_HBM_GBS, "bytes": bsc_bytes}},
     }
-    if args.bsc_only:
+    if args.config2_only:
         return out
     log("streaming: one push per gantry angle")
     out["streaming"] = bench_stream(torch, gen, H, h, spec, params, hist)
@@ -496,7 +496,7 @@ def bench_batch(torch, gen, H, dev, reps=5):
     one after another on one stream."""
     specs = gen.batch_specs()
     params = H.make_params()
-    jobs, keep, total = [], [], 0
+    jobs, keep, total, stats = [], [], 0, []
     for sp in specs:
         h = gen.generate(sp)
         hist = H.Histories.from_numpy(h, dev)
@@ -507,8 +507,10 @@ def bench_batch(torch, gen, H, dev, reps=5):
                     sc_mask=torch.zeros(V, dtype=torch.uint8, device=dev),
                     msc_mask=torch.zeros(V, dtype=torch.uint8, device=dev),
                     sm_mask=torch.zeros(V, dtype=torch.uint8, device=dev))
-        jobs.append(H.make_job(H.HULL_OP_ALL, hist, sp.grid, params, **outs))
+        st = torch.zeros(6, dtype=torch.int64, device=dev)
+        jobs.append(H.make_job(H.HULL_OP_ALL, hist, sp.grid, params, stats=st, **outs))
         keep.append((hist, outs, sp))
+        stats.append(st)
         total += sp.n_hist
     stream = torch.cuda.current_stream()
     ws_bytes = max(H.hull_workspace_bytes(H.HULL_OP_ALL, sp.grid, sp.n_hist) for sp in specs)
@@ -526,6 +528,8 @@ def bench_batch(torch, gen, H, dev, reps=5):
     t_batch = timed_on(torch, stream, lambda: plan.launch(stream), reps)
     tune = plan.tuning
     plan.close()
+    visits = sum(H.stats_dict(st)["n_visits_low"] + H.stats_dict(st)["n_visits_high"]
+                 for st in stats)
     # the default launch choices in the same plan shape, for comparison
     plan = H.BatchPlan(jobs, keep=keep, tuning=H.hullmi_tuning(4, 1, 0))
     t_default = timed_on(torch, stream, lambda: plan.launch(stream), reps)
@@ -537,6 +541,7 @@ def bench_batch(torch, gen, H, dev, reps=5):
             "batched_histories_per_s": total / (t_batch * 1e-3),
             "sequential_histories_per_s": total / (t_seq * 1e-3),
             "speedup": t_seq / t_batch,
+            "voxel_visits": visits, "batched_visits_per_s": visits / (t_batch * 1e-3),
             "tuning": tune.as_dict(),
             "plan_s_incl_autotune": t_plan_s}
 
@@ -727,8 +732,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving figures")
     ap.add_argument("--serve-small", action="store_true",
                     help="serve 300 requests of up to 1e7 histories instead of 2000 of up to 1e8")
-    ap.add_argument("--bsc-only", action="store_true",
-                    help="time the 200x200x32 case alone (for a profile of its kernels)")
+    ap.add_argument("--config2-only", action="store_true",
+                    help="time the 200x200x32 case alone (its per-rule calls, FDK and binned SC; "
+                         "for a profile of their kernels)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one 256 MiB device-to-device copy: the "
                          "known-size kernel that scales hardware byte counters")
@@ -744,7 +750,7 @@ def main():
     from paper_1402_1720_amd import hullmi as H
 
     dev = torch.device("cuda:0")
-    if args.bsc_only:
+    if args.config2_only:
         print(json.dumps(config2(torch, gen, H, dev, args)), flush=True)
         return
     result, ctx = headline(torch, gen, H, dev, args)
@@ -760,7 +766,12 @@ def main():
         torch.cuda.empty_cache()
         if not args.no_batch:
             log("batch: 16 scans")
-            result["batch"] = bench_batch(torch, gen, H, dev)
+            b = bench_batch(torch, gen, H, dev)
+            # how close the batch comes to the voxel-visit rate of one large
+            # scan's counting pass: the most a single fused launch could gain
+            b["visit_rate_vs_full_scale_pass"] = (b["batched_visits_per_s"] /
+                                                  result["walk"]["visits_per_s"])
+            result["batch"] = b
             torch.cuda.empty_cache()
         if not args.no_serve:
             log("serving")
