@@ -47,7 +47,8 @@
  *     [1, 2048] or with more than 2^31 - 1 voxels, a voxel size or origin that
  *     is not finite or not positive, a non-finite threshold, n_t < 1,
  *     frac_den <= 0, frac_num < 0, an unknown mode, scope or neighbourhood.
- *   - A workspace smaller than hull_workspace_bytes() returns HULL_ENOMEM.
+ *   - A workspace smaller than hull_workspace_bytes() returns HULL_ENOMEM
+ *     (for the counting ops, smaller than their minimum; see there).
  *   - A failed launch returns HULL_EDEVICE.
  */
 #ifndef HULLMI_H
@@ -169,7 +170,12 @@ const char *hull_strerror(int status);
 /* Device workspace (bytes, 256-byte aligned start expected) that `op` needs
  * for a grid and n histories (fbp may be NULL unless op is HULL_OP_FBP,
  * HULL_OP_FBP_CUT or HULL_OP_SC_BINNED, where it gives the bins).
- * Returns 0 when nothing is needed, or (size_t)-1 on invalid arguments. */
+ * Returns 0 when nothing is needed, or (size_t)-1 on invalid arguments.
+ * The counting ops (SC, MSC, SM, ALL) take their histories in internal
+ * batches of at most 2^26: this is the size for batches of min(n, 2^26),
+ * about 180 bytes per history. They also run in any smaller workspace of at
+ * least hull_workspace_bytes(op, grid, min(n, 65536)), in smaller batches
+ * (the largest that fit): the same results, with more launches. */
 size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n,
                             const hullmi_fbp_params *fbp);
 

@@ -200,12 +200,11 @@ constexpr int kRangesPerGroup = 2;
 // ranges, which caps this at 8 for 256 workgroups.
 constexpr int kRangesPerGroupAlone = 8;
 
-// Layout of the slice-binned counting workspace for batches of up to
-// min(n, kBatch) histories. With base == nullptr only the size is computed.
-BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
+// Layout of the slice-binned counting workspace for internal batches of B
+// histories. With base == nullptr only the size is computed.
+BinWs bin_ws_layout(const hullmi_grid *g, int64_t B, void *base, size_t *bytes)
 {
     BinWs w;
-    const int64_t B = std::max<int64_t>(1, std::min<int64_t>(n, kBatch));
     w.B = B;
     w.nz = g->nz;
     w.nl = length_classes(g);
@@ -221,12 +220,11 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     w.slot_words = (w.tile_words + 3) & ~3;
     w.min_ranges = kMaxWalkGroups * kRangesPerGroup;
     // ranges: P0 = max(min_ranges, ceil(I / kItemsPerRange)) coarse ranges,
-    // each split into at most ceil(items / kItemsPerRange) pieces:
-    // P <= 2 P0 + I / kItemsPerRange
+    // each split into ceil(items / kItemsPerRange) <= 1 + items / kItemsPerRange
+    // pieces: P <= P0 + I / kItemsPerRange <= min_ranges + 2 ceil(I / kItemsPerRange)
     const int64_t imax = B * kMaxSlicesPerLine;
-    const int64_t p0 = std::max<int64_t>(kMaxWalkGroups * kRangesPerGroup,
-                                         (imax + kItemsPerRange - 1) / kItemsPerRange);
-    w.max_ranges = (int)(2 * p0 + (imax + kItemsPerRange - 1) / kItemsPerRange);
+    w.max_ranges = (int)(kMaxWalkGroups * kRangesPerGroup +
+                         2 * ((imax + kItemsPerRange - 1) / kItemsPerRange));
     w.max_slots = w.max_ranges + w.ntiles;
     char *b = reinterpret_cast<char *>(base);
     size_t off = 0;
@@ -255,11 +253,37 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t n, void *base, size_t *bytes)
     return w;
 }
 
-size_t counts_ws_bytes(const hullmi_grid *g, int64_t n)
+inline int64_t batch_of(int64_t n, int64_t cap) { return std::max<int64_t>(1, std::min(n, cap)); }
+
+size_t bin_ws_bytes(const hullmi_grid *g, int64_t B)
 {
     size_t bytes = 0;
-    bin_ws_layout(g, n, nullptr, &bytes);
+    bin_ws_layout(g, B, nullptr, &bytes);
     return bytes;
+}
+
+// Counting workspace for n histories in the largest internal batches.
+size_t counts_ws_bytes(const hullmi_grid *g, int64_t n) { return bin_ws_bytes(g, batch_of(n, kBatch)); }
+
+// The smallest counting workspace that n histories can run in.
+size_t counts_ws_min_bytes(const hullmi_grid *g, int64_t n)
+{
+    return bin_ws_bytes(g, batch_of(n, kMinBatch));
+}
+
+// The largest internal batch for n histories whose workspace fits in avail
+// bytes (the size grows with the batch), 0 when not even the smallest fits.
+int64_t batch_for(const hullmi_grid *g, int64_t n, size_t avail)
+{
+    int64_t hi = batch_of(n, kBatch);
+    if (bin_ws_bytes(g, hi) <= avail) return hi;
+    int64_t lo = batch_of(n, kMinBatch);
+    if (bin_ws_bytes(g, lo) > avail) return 0;
+    while (hi - lo > 1) {   // bytes(lo) fits, bytes(hi) does not
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (bin_ws_bytes(g, mid) <= avail) lo = mid; else hi = mid;
+    }
+    return lo;
 }
 
 struct FbpWs {
@@ -301,19 +325,22 @@ FbpWs fbp_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, void *base
 }
 
 // Zero (unless accumulating) and count: the shared core of every hull call.
-// Histories go through in batches of up to kBatch; counts add up across them.
+// Histories go through in internal batches, as large as the workspace allows
+// (up to kBatch); counts add up across them.
 int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, float e_high, int32_t *N,
-               int32_t *M, uint32_t flags, hullmi_stats *stats, void *ws, hipStream_t s,
-               const CountOpts &o)
+               int32_t *M, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
+               hipStream_t s, const CountOpts &o)
 {
     const int64_t V = voxels(g);
+    const int64_t B = h->n > 0 ? batch_for(g, h->n, ws_bytes) : 1;
+    if (B == 0) return HULL_ENOMEM;
     if (!(flags & HULL_ACCUMULATE)) {
         fill_u32(N, 0u, N ? V : 0, s);
         fill_u32(M, 0u, M ? V : 0, s);
         fill_u64(stats, 0ull, stats ? 6 : 0, s);
     }
     if (h->n == 0) return launch_status();
-    BinWs w = bin_ws_layout(g, h->n, ws, nullptr);
+    BinWs w = bin_ws_layout(g, B, ws, nullptr);
     const DevProps dp = dev_props();
     const size_t tile_bytes = (size_t)tile_lds_bytes(w.stride, g->ny);   // tile + control words
     const bool tile_ok =
@@ -353,7 +380,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
                                                        M != nullptr, tile_ok ? 1 : 0, wb, stats);
         done();
         mark(HULL_PROF_SCAN);
-        k_bin_scan_blocks<<<wb.nsub, 256, 0, s>>>(wb);
+        k_bin_scan_blocks<<<wb.nsub, 256, (size_t)wb.nblk * 4, s>>>(wb);
         done();
         mark(HULL_PROF_PLAN);
         k_bin_plan<<<1, 1024, 0, s>>>(wb);
@@ -452,8 +479,8 @@ int sc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_lo
             hipStream_t s, const CountOpts &o)
 {
     if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low)) return HULL_EINVAL;
-    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, o);
+    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_min_bytes(grid, hist->n))) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, ws_bytes, s, o);
     if (rc != HULL_OK) return rc;
     if (mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, mask, voxels(grid));
     return launch_status();
@@ -466,8 +493,8 @@ int msc_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_l
     if (!hist_ok(hist) || !grid_ok(grid) || !N || !std::isfinite(wepl_low) ||
         !msc_args_ok(n_t, mode, nbr))
         return HULL_EINVAL;
-    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_bytes(grid, hist->n))) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, s, o);
+    if (hist->n > 0 && (!ws || ws_bytes < counts_ws_min_bytes(grid, hist->n))) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, wepl_low, 0.0f, N, nullptr, flags, stats, ws, ws_bytes, s, o);
     if (rc != HULL_OK) return rc;
     return run_msc_mask(grid, N, mask, n_t, mode, nbr, s);
 }
@@ -480,12 +507,13 @@ int sm_impl(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_hi
     if (!hist_ok(hist) || !grid_ok(grid) || !M || !std::isfinite(wepl_high) ||
         !sm_args_ok(frac_num, frac_den, mode, scope, nbr))
         return HULL_EINVAL;
-    const size_t cw = counts_ws_bytes(grid, hist->n);
-    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats, ws, s, o);
+    // the rule's part of the workspace first, the counting part after it
+    const size_t rw = sm_ws_bytes(grid);
+    if (!ws || ws_bytes < rw + counts_ws_min_bytes(grid, hist->n)) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, 0.0f, wepl_high, nullptr, M, flags, stats,
+                        reinterpret_cast<char *>(ws) + rw, ws_bytes - rw, s, o);
     if (rc != HULL_OK) return rc;
-    return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr,
-                       reinterpret_cast<char *>(ws) + cw, s);
+    return run_sm_mask(grid, M, mask, frac_num, frac_den, mode, scope, nbr, ws, s);
 }
 
 int all_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
@@ -498,16 +526,17 @@ int all_impl(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
     if (msc_mask && !msc_args_ok(p->msc_n_t, p->msc_mode, p->nbr)) return HULL_EINVAL;
     if (sm_mask && !sm_args_ok(p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope, p->nbr))
         return HULL_EINVAL;
-    const size_t cw = counts_ws_bytes(grid, hist->n);
-    if (!ws || ws_bytes < cw + sm_ws_bytes(grid)) return HULL_ENOMEM;
-    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats, ws, s, o);
+    const size_t rw = sm_ws_bytes(grid);   // the rules' part first, the counting part after it
+    if (!ws || ws_bytes < rw + counts_ws_min_bytes(grid, hist->n)) return HULL_ENOMEM;
+    int rc = run_counts(hist, grid, p->wepl_low, p->wepl_high, N, M, flags, stats,
+                        reinterpret_cast<char *>(ws) + rw, ws_bytes - rw, s, o);
     if (rc != HULL_OK) return rc;
     if (sc_mask) k_sc_mask<<<blocks_for(voxels(grid)), kBlock, 0, s>>>(N, sc_mask, voxels(grid));
     rc = launch_status();
     if (rc == HULL_OK) rc = run_msc_mask(grid, N, msc_mask, p->msc_n_t, p->msc_mode, p->nbr, s);
     if (rc == HULL_OK)
         rc = run_sm_mask(grid, M, sm_mask, p->sm_frac_num, p->sm_frac_den, p->sm_mode, p->sm_scope,
-                         p->nbr, reinterpret_cast<char *>(ws) + cw, s);
+                         p->nbr, ws, s);
     return rc;
 }
 
@@ -840,9 +869,10 @@ int masks_from_counts(const hullmi_grid *g, const hullmi_params *p, const int32_
 }
 
 int counts_accumulate(const hullmi_histories *h, const hullmi_grid *g, const hullmi_params *p,
-                      int32_t *N, int32_t *M, hullmi_stats *stats, void *ws, hipStream_t s)
+                      int32_t *N, int32_t *M, hullmi_stats *stats, void *ws, size_t ws_bytes,
+                      hipStream_t s)
 {
-    return run_counts(h, g, p->wepl_low, p->wepl_high, N, M, HULL_ACCUMULATE, stats, ws, s,
+    return run_counts(h, g, p->wepl_low, p->wepl_high, N, M, HULL_ACCUMULATE, stats, ws, ws_bytes, s,
                       CountOpts{});
 }
 

@@ -269,31 +269,6 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
     }
 }
 
-// One block per sub-bin: exclusive scan of its per-block counts, in place.
-__global__ void __launch_bounds__(256) k_bin_scan_blocks(BinWs w)
-{
-    __shared__ uint32_t part[256];
-    uint32_t *row = w.blk + (int64_t)blockIdx.x * w.nblk;
-    const int per = (w.nblk + 255) / 256;
-    const int b0 = threadIdx.x * per;
-    uint32_t s = 0;
-    for (int i = 0; i < per && b0 + i < w.nblk; ++i) s += row[b0 + i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int t = 0; t < 256; ++t) { const uint32_t v = part[t]; part[t] = acc; acc += v; }
-        w.sub_total[blockIdx.x] = acc;
-    }
-    __syncthreads();
-    uint32_t acc = part[threadIdx.x];
-    for (int i = 0; i < per && b0 + i < w.nblk; ++i) {
-        const uint32_t v = row[b0 + i];
-        row[b0 + i] = acc;
-        acc += v;
-    }
-}
-
 // Exclusive scan of get(0..n) into out[0..n) by one block (wave64 shuffles
 // and one LDS pass over the wave totals); returns the total in every thread.
 template <typename T, class Get>
@@ -330,6 +305,24 @@ __device__ T block_exclusive_scan(int n, Get get, T *out, T *sh)
     return total;
 }
 
+// One block per sub-bin: exclusive scan of its per-block counts, in place.
+// The row is staged in LDS with coalesced loads, scanned there (each thread a
+// contiguous chunk, then wave shuffles over the chunk sums) and written back
+// coalesced.
+__global__ void __launch_bounds__(256) k_bin_scan_blocks(BinWs w)
+{
+    extern __shared__ uint32_t rowl[];   // [nblk]
+    __shared__ uint32_t sh[5];
+    uint32_t *row = w.blk + (int64_t)blockIdx.x * w.nblk;
+    const int n = w.nblk;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) rowl[i] = row[i];
+    __syncthreads();
+    const uint32_t total =
+        block_exclusive_scan<uint32_t>(n, [&](int i) { return rowl[i]; }, rowl, sh);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = rowl[i];
+    if (threadIdx.x == 0) w.sub_total[blockIdx.x] = total;
+}
+
 __device__ __forceinline__ unsigned long long item_work(const BinWs &w, int sub)
 {
     const int lc = sub % w.nl;
@@ -344,6 +337,7 @@ __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
 {
     __shared__ unsigned long long shw[17];
     __shared__ uint32_t shu[17];
+    __shared__ unsigned long long wp[kMaxSubBins];   // the work prefix, for the searches
     const int nreg = w.ntiles * w.nl;
     const uint32_t total = block_exclusive_scan<uint32_t>(
         w.nsub, [&](int i) { return w.sub_total[i]; }, w.sub_start, shu);
@@ -352,6 +346,8 @@ __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
         nreg, [&](int i) { return (unsigned long long)w.sub_total[i] * item_work(w, i); },
         w.wprefix, shw);
     if (threadIdx.x == 0) w.wprefix[nreg] = wtot;
+    __syncthreads();
+    for (int i = threadIdx.x; i <= nreg; i += blockDim.x) wp[i] = w.wprefix[i];
     __syncthreads();
     const uint32_t I = w.sub_start[nreg];
     for (int t = threadIdx.x; t <= w.ntiles; t += blockDim.x) w.tile_start[t] = w.sub_start[t * w.nl];
@@ -367,10 +363,10 @@ __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
             int l = 0, h = nreg;   // last sub-bin s with wprefix[s] <= X
             while (l < h) {
                 const int m = (l + h + 1) >> 1;
-                if (w.wprefix[m] <= X) l = m; else h = m - 1;
+                if (wp[m] <= X) l = m; else h = m - 1;
             }
             const unsigned long long per = item_work(w, l);
-            unsigned long long k = (X - w.wprefix[l] + per - 1) / per;
+            unsigned long long k = (X - wp[l] + per - 1) / per;
             if (k > w.sub_total[l]) k = w.sub_total[l];
             item = min(w.sub_start[l] + (uint32_t)k, I);
         }
@@ -396,6 +392,7 @@ __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
         w.ctl[kCtlOverflowStart] = (int32_t)w.sub_start[w.nsub - 2];
         w.ctl[kCtlOverflowCount] = (int32_t)(w.sub_total[w.nsub - 2] + w.sub_total[w.nsub - 1]);
         w.ctl[kCtlOverflowLow] = (int32_t)w.sub_total[w.nsub - 2];
+        w.ctl[kCtlCoarse] = (int32_t)P0;
     }
 }
 
@@ -487,26 +484,30 @@ __device__ __forceinline__ void barrier_after_asm_lds()
     __syncthreads();
 }
 
-// Persistent workgroups over the ranges; a range is cut at slice boundaries
+// Persistent workgroups over the coarse ranges of equal estimated work (dealt
+// round-robin); a coarse range is cut at its pieces' and at slice boundaries
 // into segments, each accumulated in the LDS copy of its slice and written to
-// its partial slot. Items carry their slice-walk state (k_item_setup), so a
-// lane only runs the loop; the next item's state is loaded while the current
-// one is walked.
+// its partial slot. A workgroup walks every piece of its coarse ranges, so the
+// work stays even when long ranges are split. Items carry their slice-walk
+// state (k_item_setup), so a lane only runs the loop; the next item's state is
+// loaded while the current one is walked.
 __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, int ny)
 {
     extern __shared__ uint32_t lds[];   // tile (slot_words), then 2 control words
     uint32_t *tile = lds;
     uint32_t *seg = lds + w.slot_words;
     const int nranges = w.ctl[kCtlRanges];
+    const int ncoarse = w.ctl[kCtlCoarse];
     // LDS byte address of the tile (the low 32 bits of a local pointer)
     const uint32_t tile_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)tile;
-    for (int r = blockIdx.x; r < nranges; r += gridDim.x) {
-        uint32_t x = w.range_start[r];
-        const uint32_t b = w.range_start[r + 1];
+    for (int r = blockIdx.x; r < ncoarse; r += gridDim.x) {
+        uint32_t x = w.range_coarse[r];
+        const uint32_t b = w.range_coarse[r + 1];
         while (x < b) {
             if (threadIdx.x == 0) {
                 const int t = count_le(w.tile_start, 0, w.ntiles, x) - 1;   // slice holding x
-                seg[0] = min(b, w.tile_start[t + 1]);
+                const int p = count_le(w.range_start, 0, nranges + 1, x) - 1;   // piece holding x
+                seg[0] = min(min(b, w.tile_start[t + 1]), w.range_start[p + 1]);
                 seg[1] = (uint32_t)slot_of(w, nranges, x);
             }
             for (int i = threadIdx.x; i < w.slot_words; i += blockDim.x) tile[i] = 0;

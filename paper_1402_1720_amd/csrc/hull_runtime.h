@@ -71,9 +71,11 @@ bool grid_valid(const hullmi_grid *g);
 bool hist_valid(const hullmi_histories *h);
 size_t counting_ws_bytes(const hullmi_grid *g, int64_t n);   // counting, up to n histories a call
 size_t rules_ws_bytes(const hullmi_grid *g);                 // masks from counts
-// Adds the counts of h to N and M (and its counters to stats).
+// Adds the counts of h to N and M (and its counters to stats), with a counting
+// workspace of ws_bytes.
 int counts_accumulate(const hullmi_histories *h, const hullmi_grid *g, const hullmi_params *p,
-                      int32_t *N, int32_t *M, hullmi_stats *stats, void *ws, hipStream_t s);
+                      int32_t *N, int32_t *M, hullmi_stats *stats, void *ws, size_t ws_bytes,
+                      hipStream_t s);
 // The SC, MSC and SM masks of counts N and M (each mask may be null).
 int masks_from_counts(const hullmi_grid *g, const hullmi_params *p, const int32_t *N,
                       const int32_t *M, uint8_t *sc, uint8_t *msc, uint8_t *sm, void *ws,

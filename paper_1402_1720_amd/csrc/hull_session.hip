@@ -108,7 +108,7 @@ int flush(hullmi_session *s, int k)
     hullmi_histories h{field(s, k, 0), field(s, k, 1), field(s, k, 2), field(s, k, 3),
                        field(s, k, 4), field(s, k, 5), field(s, k, 6), field(s, k, 7), s->fill[k]};
     const int rc = hullmi::counts_accumulate(&h, &s->grid, &s->params, s->N, s->M, s->stats, s->ws,
-                                             s->compute);
+                                             s->count_ws, s->compute);
     if (rc != HULL_OK) return rc;
     if (hipEventRecord(s->counted[k], s->compute) != hipSuccess) return HULL_EDEVICE;
     s->fill[k] = 0;

@@ -45,9 +45,10 @@ def test_workspace_sizes():
     assert sc > 100 * 24                       # quantised endpoints at least
     assert H.hull_workspace_bytes(H.HULL_OP_MSC, g, 100) == sc
     assert H.hull_workspace_bytes(H.HULL_OP_ALL, g, 100) >= sc + 8 * 4
-    # the batch caps the workspace: 2^24 histories at most
-    big = H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 24)
+    # the internal batch caps the workspace: 2^26 histories at most
+    big = H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 26)
     assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 31 - 1) == big
+    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 26 - 2 ** 16) < big
     f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
     nb = 300 * 22 * 180
     assert H.hull_workspace_bytes(H.HULL_OP_FBP, g, 100, f) >= nb * 16
@@ -112,6 +113,16 @@ def test_mode_and_threshold_checks():
     assert L.hull_sm(*smargs(3, 5, 0, 0, FAKE, 64)) == H.HULL_ENOMEM
     sc_args = (ctypes.byref(h), ctypes.byref(g), 1.0, FAKE, None, 0, None, FAKE, 64, None)
     assert L.hull_sc(*sc_args) == H.HULL_ENOMEM
+    # the counting ops run in any workspace down to that of a 2^16-history
+    # batch: one byte less is refused before anything is enqueued
+    big = _hist(n=1_000_000)
+    least = H.hull_workspace_bytes(H.HULL_OP_SC, g, 1 << 16)
+    assert least < H.hull_workspace_bytes(H.HULL_OP_SC, g, big.n)
+    assert L.hull_sc(ctypes.byref(big), ctypes.byref(g), 1.0, FAKE, None, 0, None, FAKE, least - 1,
+                     None) == H.HULL_ENOMEM
+    rules = H.hull_workspace_bytes(H.HULL_OP_SM, g, 1 << 16) - least
+    assert L.hull_sm(ctypes.byref(big), ctypes.byref(g), 5.0, 3, 5, 0, 0, 0, FAKE, FAKE, 0, None,
+                     FAKE, rules + least - 1, None) == H.HULL_ENOMEM
     f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
     assert L.hull_fbp(ctypes.byref(h), ctypes.byref(g), ctypes.byref(f), FAKE, None, FAKE, 16,
                       None) == H.HULL_ENOMEM

@@ -269,6 +269,36 @@ def test_range_counters_at_their_cap():
     plan.close()
 
 
+def test_split_ranges_flush_at_every_piece():
+    """Coarse ranges of equal estimated work over 3 x 65,535 short lines (3
+    voxels each) and 65,535 long ones (28 voxels) in one slice: the first two
+    hold about 85,000 short lines each, more than a 16-bit counter can take, so
+    the plan splits them into pieces of at most 65,535 items; the workgroup
+    that walks a coarse range must write out its tile at every piece boundary.
+    Two walk workgroups, one coarse range each at a time; the sums are exact."""
+    g = gen.Grid((24, 20, 4), (1.0, 1.0, 2.5))
+    short = dict(x_in=-30.0, y_in=50.7, z_in=1.1, x_out=30.0, y_out=-9.3, z_out=1.15, angle_deg=0.0)
+    long = dict(x_in=-30.0, y_in=-4.3, z_in=1.1, x_out=30.0, y_out=5.7, z_out=1.4, angle_deg=0.0)
+    ns, nl = 3 * 65_535, 65_535
+    h = {k: np.concatenate([np.full(ns, short[k], np.float32), np.full(nl, long[k], np.float32)])
+         for k in short}
+    h["wepl"] = np.full(ns + nl, 0.5, np.float32)
+    rN, rM, rst = oracle.counts(h, oracle.grid_of(g))
+    assert rN.max() == ns and rst["n_visits_low"] == 3 * ns + 28 * nl
+    hist = H.Histories.from_numpy(h, DEV)
+    V = g.voxels
+    N = torch.zeros(V, dtype=torch.int32, device=DEV)
+    M = torch.zeros(V, dtype=torch.int32, device=DEV)
+    st = torch.zeros(6, dtype=torch.int64, device=DEV)
+    job = H.make_job(H.HULL_OP_ALL, hist, g, H.make_params(), stats=st, N=N, M=M)
+    plan = H.BatchPlan([job], keep=[hist, N, M, st], tuning=H.hullmi_tuning(1, 0, 2, 1))
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(N.cpu().numpy(), rN) and np.array_equal(M.cpu().numpy(), rM)
+    assert H.stats_dict(st) == rst
+    plan.close()
+
+
 # ---------------------------------------------------------------------------
 # serving
 

@@ -31,12 +31,12 @@ def zeros(V, dtype=torch.int32):
     return torch.zeros(V, dtype=dtype, device=DEV)
 
 
-def gpu_counts(h, grid, e_low=1.0, e_high=5.0):
+def gpu_counts(h, grid, e_low=1.0, e_high=5.0, ws=None):
     hist = dev_hist(h)
     V = grid.voxels if hasattr(grid, "voxels") else int(grid.nx * grid.ny * grid.nz)
     N, M = zeros(V), zeros(V)
     st = zeros(6, torch.int64)
-    H.hull_all(hist, grid, H.make_params(wepl_low=e_low, wepl_high=e_high), N, M, stats=st)
+    H.hull_all(hist, grid, H.make_params(wepl_low=e_low, wepl_high=e_high), N, M, stats=st, ws=ws)
     torch.cuda.synchronize()
     return N.cpu().numpy(), M.cpu().numpy(), H.stats_dict(st)
 
@@ -424,12 +424,29 @@ def test_long_rows_and_far_endpoints():
     assert rN[: 1000].sum() > 0 and rN[1100:2048].sum() > 0
 
 
-def test_two_internal_batches():
-    """More than 2^24 histories run as several internal batches."""
-    spec = gen.config_spec(1, n_hist=(1 << 24) + 4097)
+def test_internal_batches_set_by_the_workspace():
+    """The counting ops take their histories in internal batches as large as
+    the workspace allows: a workspace sized for 2^18 histories runs 2^20 + 4097
+    of them in five batches, the smallest allowed workspace (2^16) in
+    seventeen, and the full-size one in one; every split gives the oracle's
+    counts."""
+    spec = gen.config_spec(2, n_hist=(1 << 20) + 4097)
     h = gen.generate(spec)
     G = oracle.grid_of(spec.grid)
-    say("two batches: oracle")
+    say("workspace batches: oracle")
     rN, rM, rst = oracle.counts(h, G)
-    gN, gM, gst = gpu_counts(h, spec.grid)
-    assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
+    for b in (1 << 16, 1 << 18, spec.n_hist):
+        ws = H.workspace(H.HULL_OP_ALL, spec.grid, b, DEV)
+        gN, gM, gst = gpu_counts(h, spec.grid, ws=ws)
+        assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst, b
+
+
+def test_workspace_below_the_smallest_batch_is_refused():
+    spec = gen.config_spec(1, n_hist=100_000)
+    hist = dev_hist(gen.generate(spec))
+    V = spec.grid.voxels
+    small = H.hull_workspace_bytes(H.HULL_OP_ALL, spec.grid, 1 << 16) - 256
+    ws = torch.empty(small, dtype=torch.uint8, device=DEV)
+    with pytest.raises(H.HullError) as e:
+        H.hull_all(hist, spec.grid, H.make_params(), zeros(V), zeros(V), ws=ws)
+    assert e.value.status == H.HULL_ENOMEM

@@ -37,15 +37,18 @@ def test_count_profile_counts_and_launches():
     assert prof2["walk"][1] == 1
 
 
-def test_count_profile_over_two_internal_batches():
-    spec = gen.config_spec(1, n_hist=(1 << 24) + 1000)
+def test_count_profile_over_internal_batches():
+    """A workspace sized for 2^19 histories runs 2^20 + 1000 in three internal
+    batches: three launches of every counting kernel."""
+    spec = gen.config_spec(1, n_hist=(1 << 20) + 1000)
     h = gen.generate(spec)
     hist = H.Histories.from_numpy(h, DEV)
     V = spec.grid.voxels
     N = torch.zeros(V, dtype=torch.int32, device=DEV)
     M = torch.zeros(V, dtype=torch.int32, device=DEV)
-    prof = H.hull_count_profile(hist, spec.grid, H.make_params(), N, M)
-    assert all(n == 2 for _, n in prof.values())
+    ws = H.workspace(H.HULL_OP_ALL, spec.grid, 1 << 19, DEV)
+    prof = H.hull_count_profile(hist, spec.grid, H.make_params(), N, M, ws=ws)
+    assert all(n == 3 for _, n in prof.values())
     N2 = torch.zeros_like(N)
     M2 = torch.zeros_like(M)
     H.hull_all(hist, spec.grid, H.make_params(), N2, M2)
