@@ -380,7 +380,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
                                                        M != nullptr, tile_ok ? 1 : 0, wb, stats);
         done();
         mark(HULL_PROF_SCAN);
-        k_bin_scan_blocks<<<wb.nsub, 256, (size_t)wb.nblk * 4, s>>>(wb);
+        k_bin_scan_blocks<<<wb.nsub, 256, (size_t)(wb.nblk + wb.nblk / 32 + 1) * 4, s>>>(wb);
         done();
         mark(HULL_PROF_PLAN);
         k_bin_plan<<<1, 1024, 0, s>>>(wb);

@@ -271,8 +271,8 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
 
 // Exclusive scan of get(0..n) into out[0..n) by one block (wave64 shuffles
 // and one LDS pass over the wave totals); returns the total in every thread.
-template <typename T, class Get>
-__device__ T block_exclusive_scan(int n, Get get, T *out, T *sh)
+template <typename T, class Get, class Put>
+__device__ T block_exclusive_scan_to(int n, Get get, Put put, T *sh)
 {
     const int nt = (int)blockDim.x;
     const int per = (n + nt - 1) / nt;
@@ -297,7 +297,7 @@ __device__ T block_exclusive_scan(int n, Get get, T *out, T *sh)
     T acc = sh[wid] + inc - s;
     for (int i = 0; i < per && b0 + i < n; ++i) {
         const T v = get(b0 + i);
-        out[b0 + i] = acc;
+        put(b0 + i, acc);
         acc += v;
     }
     const T total = sh[nt >> 6];
@@ -305,21 +305,31 @@ __device__ T block_exclusive_scan(int n, Get get, T *out, T *sh)
     return total;
 }
 
+template <typename T, class Get>
+__device__ T block_exclusive_scan(int n, Get get, T *out, T *sh)
+{
+    return block_exclusive_scan_to<T>(n, get, [&](int i, T v) { out[i] = v; }, sh);
+}
+
 // One block per sub-bin: exclusive scan of its per-block counts, in place.
 // The row is staged in LDS with coalesced loads, scanned there (each thread a
 // contiguous chunk, then wave shuffles over the chunk sums) and written back
-// coalesced.
+// coalesced. One pad word after every 32 puts the chunks of a wave's lanes,
+// 32 words each for 8192 blocks, in different LDS banks.
+__device__ __forceinline__ int scan_slot(int i) { return i + (i >> 5); }
+
 __global__ void __launch_bounds__(256) k_bin_scan_blocks(BinWs w)
 {
-    extern __shared__ uint32_t rowl[];   // [nblk]
+    extern __shared__ uint32_t rowl[];   // [scan_slot(nblk)]
     __shared__ uint32_t sh[5];
     uint32_t *row = w.blk + (int64_t)blockIdx.x * w.nblk;
     const int n = w.nblk;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) rowl[i] = row[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) rowl[scan_slot(i)] = row[i];
     __syncthreads();
-    const uint32_t total =
-        block_exclusive_scan<uint32_t>(n, [&](int i) { return rowl[i]; }, rowl, sh);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = rowl[i];
+    const uint32_t total = block_exclusive_scan_to<uint32_t>(
+        n, [&](int i) { return rowl[scan_slot(i)]; },
+        [&](int i, uint32_t v) { rowl[scan_slot(i)] = v; }, sh);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = rowl[scan_slot(i)];
     if (threadIdx.x == 0) w.sub_total[blockIdx.x] = total;
 }
 
