@@ -110,12 +110,13 @@ constexpr uint32_t kStateNoCorner = 1u << 24;
 
 __device__ __forceinline__ uint4 pack_state(const SliceState &s, bool no_corner)
 {
-    if (s.first < 0) return make_uint4(0u, 0u, kStateEmpty, 0u);
-    return make_uint4((uint32_t)s.d, ((uint32_t)s.first & 0xffffu) | (uint32_t)s.last << 16,
-                      (uint32_t)s.ay | (uint32_t)(s.sx < 0) << 19 | (uint32_t)(s.sy < 0) << 20 |
-                          ((uint32_t)s.first >> 16) << 22 | ((uint32_t)s.last >> 16) << 23 |
-                          (no_corner ? kStateNoCorner : 0u),
-                      (uint32_t)s.ax);
+    const bool e = s.first < 0;
+    const uint4 r = make_uint4((uint32_t)s.d, ((uint32_t)s.first & 0xffffu) | (uint32_t)s.last << 16,
+                               (uint32_t)s.ay | (uint32_t)(s.sx < 0) << 19 | (uint32_t)(s.sy < 0) << 20 |
+                                   ((uint32_t)s.first >> 16) << 22 | ((uint32_t)s.last >> 16) << 23 |
+                                   (no_corner ? kStateNoCorner : 0u),
+                               (uint32_t)s.ax);
+    return make_uint4(e ? 0u : r.x, e ? 0u : r.y, e ? kStateEmpty : r.z, e ? 0u : r.w);
 }
 
 // Approximate number of voxels of the line inside slice k (FP32, only used to

@@ -356,57 +356,62 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
                                                 int ny, bool check_z, int &cx, int &cy,
                                                 double *dxy)
 {
+    // Every lane computes every case and selects: the per-lane branches
+    // (axis not moving, entry axis, range checks) would otherwise cost a
+    // divergent branch each.
     const int n[3] = {nx, ny, 1};
     double A[3], en[3];
     int g[3];
+    bool ok = true;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        if (D[b] == 0 && (P[b] < 0 || P[b] >= kQ * n[b])) return false;
+        ok &= !((D[b] == 0) & ((P[b] < 0) | (P[b] >= kQ * n[b])));
         A[b] = (double)(D[b] < 0 ? -D[b] : D[b]);
         en[b] = (double)(D[b] > 0 ? -P[b] : P[b] - kQ * n[b]);
         g[b] = D[b] < 0;
     }
+    // entry axis: the moving axis whose slab is entered last (largest en / A),
+    // ties to the axis that steps down
     int wa = -1;
     double ew = 0.0, aw = 1.0;
     int gw = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        if (D[b] == 0) continue;
-        if (wa >= 0) {
-            const double l = en[b] * aw, r = ew * A[b];
-            if (!(l > r || (l == r && g[b] > gw))) continue;
-        }
-        wa = b; ew = en[b]; aw = A[b]; gw = g[b];
+        const double l = en[b] * aw, r = ew * A[b];
+        const bool take = (D[b] != 0) & ((wa < 0) | (l > r) | ((l == r) & (g[b] > gw)));
+        wa = take ? b : wa;
+        ew = take ? en[b] : ew;
+        aw = take ? A[b] : aw;
+        gw = take ? g[b] : gw;
     }
     // products and sums below are exact in a double, so an FMA gives the same values
-    if (check_z && wa != 2 && D[2] != 0) {
+    if (check_z) {
         const double num = __builtin_fma((double)P[2], aw, (double)D[2] * ew);
         const double lim = (double)kQ * aw;
-        if (gw && D[2] < 0 ? (num <= 0.0 || num > lim) : (num < 0.0 || num >= lim)) return false;
+        const bool up = (gw != 0) & (D[2] < 0);
+        const bool bad = (up & ((num <= 0.0) | (num > lim))) | (!up & ((num < 0.0) | (num >= lim)));
+        ok &= !((wa != 2) & (D[2] != 0) & bad);
     }
     const double den = (double)kQ * aw;
     const double rden = __builtin_amdgcn_rcp(den);
     int c[2];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-        if (b == wa) {
-            c[b] = D[b] > 0 ? 0 : n[b] - 1;
-        } else if (D[b] == 0) {
-            c[b] = P[b] >> 10;
-        } else {
-            const double num = __builtin_fma((double)P[b], aw, (double)D[b] * ew);
-            const double lim = (double)n[b] * den;
-            const bool up = gw && D[b] < 0;
-            if (up ? (num <= 0.0 || num > lim) : (num < 0.0 || num >= lim)) return false;
-            // up: ceil(num / den) - 1 = floor((num - 1) / den); the estimate is
-            // off by at most one, fixed by two exact comparisons
-            const double a = up ? num - 1.0 : num;
-            int q = (int)floor(a * rden);
-            q = max(0, min(q, n[b] - 1));
-            if ((double)q * den > a) --q;
-            if ((double)(q + 1) * den <= a) ++q;
-            c[b] = q;
-        }
+        const double num = __builtin_fma((double)P[b], aw, (double)D[b] * ew);
+        const double lim = (double)n[b] * den;
+        const bool up = (gw != 0) & (D[b] < 0);
+        const bool bad = (up & ((num <= 0.0) | (num > lim))) | (!up & ((num < 0.0) | (num >= lim)));
+        // up: ceil(num / den) - 1 = floor((num - 1) / den); the estimate is
+        // off by at most one, fixed by two exact comparisons (clamped first,
+        // so that the conversion stays in range where the line misses)
+        const double a = up ? num - 1.0 : num;
+        const double e = fmin(fmax(floor(a * rden), 0.0), (double)(n[b] - 1));
+        int q = (int)e;
+        q -= (double)q * den > a ? 1 : 0;
+        q += (double)(q + 1) * den <= a ? 1 : 0;
+        const bool moving = (D[b] != 0) & (b != wa);
+        ok &= !(moving & bad);
+        c[b] = b == wa ? (D[b] > 0 ? 0 : n[b] - 1) : (D[b] == 0 ? P[b] >> 10 : q);
     }
     cx = c[0];
     cy = c[1];
@@ -415,7 +420,7 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
         const int32_t ey = D[1] > 0 ? kQ * (c[1] + 1) - P[1] : (D[1] < 0 ? P[1] - kQ * c[1] : 1);
         *dxy = 2.0 * __builtin_fma((double)ex, A[1], -((double)ey * A[0])) + (double)(g[0] - g[1]);
     }
-    return true;
+    return ok;
 }
 
 __device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
@@ -427,18 +432,18 @@ __device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int 
     const int32_t R[3] = {-D[0], -D[1], -D[2]};
     int fx, fy, lx, ly;
     double d;
-    if (!slice_entry_f64(P, D, nx, ny, true, fx, fy, &d) ||
-        !slice_entry_f64(Q, R, nx, ny, false, lx, ly, nullptr)) {
-        s.d = 0; s.first = -1; s.last = -1; s.ax = 0; s.ay = 0; s.sx = 1; s.sy = 1;
-        return;
-    }
-    s.d = (int32_t)d;   // below 2^31 in magnitude on a tile line
-    s.first = fx + stride * fy;
-    s.last = lx + stride * ly;
-    s.ax = D[0] < 0 ? -D[0] : D[0];
-    s.ay = D[1] < 0 ? -D[1] : D[1];
-    s.sx = D[0] > 0 ? 1 : -1;
-    s.sy = D[1] > 0 ? 1 : -1;
+    const bool in_first = slice_entry_f64(P, D, nx, ny, true, fx, fy, &d);
+    const bool in_last = slice_entry_f64(Q, R, nx, ny, false, lx, ly, nullptr);
+    // selected rather than branched on: a line that misses the slice gets
+    // first = last = -1 and zeros
+    const bool in = in_first & in_last;
+    s.d = (int32_t)(in ? d : 0.0);   // below 2^31 in magnitude on a tile line
+    s.first = in ? fx + stride * fy : -1;
+    s.last = in ? lx + stride * ly : -1;
+    s.ax = in ? (D[0] < 0 ? -D[0] : D[0]) : 0;
+    s.ay = in ? (D[1] < 0 ? -D[1] : D[1]) : 0;
+    s.sx = (in & (D[0] <= 0)) ? -1 : 1;
+    s.sy = (in & (D[1] <= 0)) ? -1 : 1;
 }
 
 // Whether A_i is not empty, exactly when walk_init returns true: the entry key
