@@ -470,15 +470,19 @@ __global__ void __launch_bounds__(256) k_item_setup(BinWs w, int nx, int ny)
     // a thread's items increase, so its slice tile only moves forward; the
     // next item's record is in flight while the current one is set up
     int t = p < n ? count_le(ts, 0, w.ntiles, (uint32_t)p) - 1 : 0;
+    int k = t % w.nz;   // the slice of tile t (tiles are class-major)
     uint4 nxt = p < n ? w.item[p] : make_uint4(0u, 0u, 0u, 0u);
     for (; p < n; p += stride) {
         const uint4 cur = nxt;
         if (p + stride < n) nxt = w.item[p + stride];
-        while (ts[t + 1] <= (uint32_t)p) ++t;   // slice tile of p
+        while (ts[t + 1] <= (uint32_t)p) {   // slice tile of p
+            ++t;
+            k = k + 1 == w.nz ? 0 : k + 1;
+        }
         int q[6];
         unpack_line(cur, q);
         SliceState st;
-        slice_state_tile(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, w.stride, t % w.nz, st);
+        slice_state_tile(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, w.stride, k, st);
         const bool nc = (st.d & 1) || corner_free(q[0], q[1], q[3] - q[0], q[4] - q[1]);
         w.item[p] = pack_state(st, nc);
     }

@@ -349,9 +349,10 @@ struct SliceState {
 // (2^24 after the slice shift of at most 2047 slices) every entry distance is
 // below 2^25 and every |D| below 2^24, so every product below is below 2^49
 // and every sum below 2^51: all exact in a double, and the results equal
-// those of the integer set-up. FP64 multiplies run at the FP32 rate, the
-// 64-bit integer ones they replace at a quarter of it. A tile line (all
-// coordinates below 2^20, |D| < 2^19 on x and y) is well inside this range.
+// those of the integer set-up. FP64 operations issue at half the FP32 rate,
+// 64-bit integer multiplies at a quarter of it. The binned SC's carve lines
+// (from a source far outside the grid) use this form; tile lines use the
+// 24-bit integer one below.
 __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_t D[3], int nx,
                                                 int ny, bool check_z, int &cx, int &cy,
                                                 double *dxy)
@@ -423,6 +424,102 @@ __device__ __forceinline__ bool slice_entry_f64(const int32_t P[3], const int32_
     return ok;
 }
 
+// Exact 48-bit product of two integers of magnitude below 2^23, from the
+// full-rate 24-bit multiplies (low 32 bits, then bits 32..47 sign-extended);
+// written out because the compiler otherwise falls back to quarter-rate 64-bit
+// multiplies where it cannot prove the operands' range.
+__device__ __forceinline__ int64_t mul_i24(int32_t a, int32_t b)
+{
+    int32_t lo, hi;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+    asm("v_mul_hi_i32_i24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+    return (int64_t)((uint64_t)(uint32_t)hi << 32 | (uint32_t)lo);
+}
+
+// Low 32 bits of the product of two integers below 2^24 (full rate).
+__device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// slice_entry_f64 in integers, for tile lines: every endpoint coordinate below
+// 2^20 in magnitude and |D| < 2^19 on x and y, slice k < 2048, so that P
+// (below 2^21 + 2^20 on z after the slice shift), D, A and the entry
+// distances all stay below 2^23 and every product is an exact 24 x 24-bit one.
+// The floor division by den = 1024 aw is (num >> 10) / aw for num >= 0, whose
+// quotient is below n <= 2048 and whose dividend then fits 32 bits: an FP32
+// estimate (off by at most one) fixed by two exact comparisons. Same
+// decisions as slice_entry_f64, at full-rate integer instructions instead of
+// half-rate FP64 ones. dxy is the decision variable in 32-bit wrap-around
+// arithmetic: exact whenever its value fits 32 bits, as it does on a tile line.
+__device__ __forceinline__ bool slice_entry_i24(const int32_t P[3], const int32_t D[3], int nx,
+                                                int ny, bool check_z, int &cx, int &cy,
+                                                int32_t *dxy)
+{
+    const int n[3] = {nx, ny, 1};
+    int32_t A[3], en[3];
+    int g[3];
+    bool ok = true;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        ok &= !((D[b] == 0) & ((P[b] < 0) | (P[b] >= kQ * n[b])));
+        A[b] = D[b] < 0 ? -D[b] : D[b];
+        en[b] = D[b] > 0 ? -P[b] : P[b] - kQ * n[b];
+        g[b] = D[b] < 0;
+    }
+    int wa = -1;
+    int32_t ew = 0, aw = 1;
+    int gw = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int64_t l = mul_i24(en[b], aw), r = mul_i24(ew, A[b]);
+        const bool take = (D[b] != 0) & ((wa < 0) | (l > r) | ((l == r) & (g[b] > gw)));
+        wa = take ? b : wa;
+        ew = take ? en[b] : ew;
+        aw = take ? A[b] : aw;
+        gw = take ? g[b] : gw;
+    }
+    if (check_z) {
+        const int64_t num = mul_i24(P[2], aw) + mul_i24(D[2], ew);
+        const int64_t lim = (int64_t)aw << 10;
+        const bool up = (gw != 0) & (D[2] < 0);
+        const bool bad = (up & ((num <= 0) | (num > lim))) | (!up & ((num < 0) | (num >= lim)));
+        ok &= !((wa != 2) & (D[2] != 0) & bad);
+    }
+    const float raw = __builtin_amdgcn_rcpf((float)aw);
+    int c[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int64_t num = mul_i24(P[b], aw) + mul_i24(D[b], ew);
+        const int64_t lim = mul_i24(n[b], aw) << 10;
+        const bool up = (gw != 0) & (D[b] < 0);
+        const bool bad = (up & ((num <= 0) | (num > lim))) | (!up & ((num < 0) | (num >= lim)));
+        // up: ceil(num / den) - 1 = floor((num - 1) / den); clamped into
+        // [0, lim) so that lanes whose line misses compute in range too
+        int64_t a = up ? num - 1 : num;
+        a = a < 0 ? 0 : (a >= lim ? lim - 1 : a);
+        const uint32_t m = (uint32_t)(a >> 10);   // below n aw <= 2^32
+        int q = (int)((float)m * raw);
+        q = max(0, min(q, n[b] - 1));
+        const uint32_t qa = mul_u24((uint32_t)q, (uint32_t)aw);   // q aw < n aw <= 2^32: exact
+        q -= qa > m ? 1 : 0;
+        q += mul_u24((uint32_t)(q + 1), (uint32_t)aw) <= m ? 1 : 0;
+        ok &= !(((D[b] != 0) & (b != wa)) & bad);
+        c[b] = b == wa ? (D[b] > 0 ? 0 : n[b] - 1) : (D[b] == 0 ? P[b] >> 10 : q);
+    }
+    cx = c[0];
+    cy = c[1];
+    if (dxy) {
+        const int32_t ex = D[0] > 0 ? kQ * (c[0] + 1) - P[0] : (D[0] < 0 ? P[0] - kQ * c[0] : 1);
+        const int32_t ey = D[1] > 0 ? kQ * (c[1] + 1) - P[1] : (D[1] < 0 ? P[1] - kQ * c[1] : 1);
+        const uint32_t cross = (uint32_t)mul_i24(ex, A[1]) - (uint32_t)mul_i24(ey, A[0]);
+        *dxy = (int32_t)(2u * cross + (uint32_t)(g[0] - g[1]));
+    }
+    return ok;
+}
+
 __device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int qox, int qoy, int qoz,
                                                  int nx, int ny, int stride, int k, SliceState &s)
 {
@@ -431,15 +528,15 @@ __device__ __forceinline__ void slice_state_tile(int qix, int qiy, int qiz, int 
     const int32_t D[3] = {qox - qix, qoy - qiy, qoz - qiz};
     const int32_t R[3] = {-D[0], -D[1], -D[2]};
     int fx, fy, lx, ly;
-    double d;
-    const bool in_first = slice_entry_f64(P, D, nx, ny, true, fx, fy, &d);
-    const bool in_last = slice_entry_f64(Q, R, nx, ny, false, lx, ly, nullptr);
+    int32_t d;
+    const bool in_first = slice_entry_i24(P, D, nx, ny, true, fx, fy, &d);
+    const bool in_last = slice_entry_i24(Q, R, nx, ny, false, lx, ly, nullptr);
     // selected rather than branched on: a line that misses the slice gets
     // first = last = -1 and zeros
     const bool in = in_first & in_last;
-    s.d = (int32_t)(in ? d : 0.0);   // below 2^31 in magnitude on a tile line
-    s.first = in ? fx + stride * fy : -1;
-    s.last = in ? lx + stride * ly : -1;
+    s.d = in ? d : 0;
+    s.first = in ? fx + (int)mul_u24((uint32_t)stride, (uint32_t)fy) : -1;
+    s.last = in ? lx + (int)mul_u24((uint32_t)stride, (uint32_t)ly) : -1;
     s.ax = in ? (D[0] < 0 ? -D[0] : D[0]) : 0;
     s.ay = in ? (D[1] < 0 ? -D[1] : D[1]) : 0;
     s.sx = (in & (D[0] <= 0)) ? -1 : 1;
