@@ -591,9 +591,11 @@ __device__ __forceinline__ bool line_meets_grid(int qix, int qiy, int qiz, int q
 // The FP32 slab of a line against the grid box: p and d in voxel units, and
 // the entry and exit parameters tlo, thi of P(t) = p + t d over the moving
 // axes (an axis with D = 0 is left out: it bounds nothing). err bounds the
-// FP32 error of tlo and thi, with room to spare: per moving axis the error of
-// (c - p) / d is below (n + 2 |p|) / |d| 2^-21 (p, d and the two operations
-// each rounded once), and err is 16 times the largest such bound.
+// FP32 error of tlo and thi, with room to spare: per moving axis t = (c - p)
+// times the hardware reciprocal of d (p, d, c - p and the product each
+// rounded once, the reciprocal within 1 ulp: below 5.5 2^-24 relative) is off
+// by less than (n + 2 |p|) / |d| 2^-21, and err is 16 times the largest such
+// bound.
 struct LineSlab {
     float p[3], d[3];
     float tlo, thi, err;
@@ -612,11 +614,11 @@ __device__ __forceinline__ void line_slab(int qix, int qiy, int qiz, int qox, in
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (b.d[a] != 0.0f) {
-            const float t0 = (0.0f - b.p[a]) / b.d[a], t1 = (n[a] - b.p[a]) / b.d[a];
+            const float r = __builtin_amdgcn_rcpf(b.d[a]);
+            const float t0 = (0.0f - b.p[a]) * r, t1 = (n[a] - b.p[a]) * r;
             tlo = fmaxf(tlo, fminf(t0, t1));
             thi = fminf(thi, fmaxf(t0, t1));
-            // a bound with room to spare: a reciprocal a few ulp off is fine
-            e = fmaxf(e, (n[a] + 2.0f * fabsf(b.p[a])) * __builtin_amdgcn_rcpf(fabsf(b.d[a])));
+            e = fmaxf(e, (n[a] + 2.0f * fabsf(b.p[a])) * fabsf(r));
         }
     }
     b.tlo = tlo;
