@@ -460,7 +460,8 @@ typedef struct hullmi_job {
  *   0 = 16, or fewer on grids of more than 128 slices);
  * run_stride: the item runs of one (class, slice, length) bin are ordered
  *   by classification block modulo this stride, so that neighbouring runs
- *   come from histories of different gantry angles (0..256; 0 = 8). */
+ *   come from histories of different gantry angles (0..256; 0 = the internal
+ *   batch's classification blocks of 8192 histories over 128, at least 1). */
 typedef struct hullmi_tuning {
     int32_t streams;
     int32_t use_graph;
