@@ -21,6 +21,7 @@ constexpr int kHistPerBlock = kBinThreads * kHistPerThread;
 constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic walk
 constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
 constexpr int kTileThreads = 1024;      // workgroup of the LDS walk
+static_assert(kTileThreads % 256 == 0, "the walk deals items in groups of four waves");
 constexpr int kItemsPerRange = 65535;   // a range holds at most this many items: each adds
                                         // at most 1 to a voxel, so a 16-bit counter holds it
 constexpr int kWorkPerItem = 16;        // fixed cost of an item in visit units (set-up)

@@ -528,14 +528,18 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
             for (int i = threadIdx.x; i < w.slot_words; i += blockDim.x) tile[i] = 0;
             __syncthreads();
             const uint32_t y = seg[0], slot = seg[1];
-            // the workgroup takes the items S at a time; within each group of
-            // S, lane l of wave q takes item l (S / 64) + q, so that a wave's
-            // 64 lines come from across the group (from many classification
-            // blocks, i.e. gantry angles) rather than from a few neighbouring
-            // runs: fewer of its LDS adds meet in one bank. The next item's
-            // record is in flight while the current line is walked.
+            // the workgroup takes the items S at a time, in groups of 256 for
+            // each four waves: lane l of the group's wave q takes item 4 l + q,
+            // so that a wave's 64 lines come from across the 256 (from about
+            // twenty item runs, i.e. classification blocks and gantry angles)
+            // rather than from five neighbouring runs, and fewer of its LDS
+            // adds meet in one bank; each 64-byte piece of the item list is
+            // still read by one group at one time. Groups of 16 waves spread
+            // the lines further but read each cache line from eight waves and
+            // were slower. The next item's record is in flight while the
+            // current line is walked.
             const uint32_t S = blockDim.x;
-            uint32_t it = x + (threadIdx.x & 63) * (S >> 6) + (threadIdx.x >> 6);
+            uint32_t it = x + (threadIdx.x & ~255u) + (threadIdx.x & 63) * 4 + ((threadIdx.x >> 6) & 3);
             uint4 c = make_uint4(0u, 0u, kStateEmpty, 0u);
             if (it < y) c = w.item[it];
             while (it < y) {
