@@ -291,11 +291,16 @@ k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *c
     };
     F8 nf{};
     fetch(base + threadIdx.x, nf);
+    // the angle of each round's last history decides the plane switch; it is
+    // loaded a round ahead, like the fields, so that no round waits for it
+    const int64_t R = blockDim.x;
+    float a_last = h.angle_deg[min(base + R, end) - 1];
     // every thread runs the same rounds: the plane switch needs the whole block
-    for (int64_t i0 = base; i0 < end; i0 += blockDim.x) {
+    for (int64_t i0 = base; i0 < end; i0 += R) {
         const int64_t i = i0 + threadIdx.x;
         const F8 f = nf;
-        fetch(i + blockDim.x, nf);
+        fetch(i + R, nf);
+        const float a_next = i0 + R < end ? h.angle_deg[min(i0 + 2 * R, end) - 1] : 0.0f;
         int k, iu, iv;
         long long fx;
         if (i < end && fbp_locate_vals(f.xi, f.yi, f.zi, f.xo, f.yo, f.zo, f.a, f.w, p, k, iu, iv, fx)) {
@@ -310,7 +315,8 @@ k_fbp_bin_lds(hullmi_histories h, FbpDev p, unsigned long long *sum, unsigned *c
             }
         }
         // the same value in every thread: the round's last history
-        const int kn = fbp_angle_bin(h.angle_deg[min(i0 + (int64_t)blockDim.x, end) - 1], p);
+        const int kn = fbp_angle_bin(a_last, p);
+        a_last = a_next;
         if (kn >= 0 && kn != kcur) {
             __syncthreads();
             if (kcur >= 0) flush(kcur);
