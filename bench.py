@@ -279,7 +279,7 @@ def headline(torch, gen, H, dev, args):
                      "frac_at_64_lanes_per_clock": walk_tops / PEAK_INT_TOPS_64,
                      "traffic": traffic["walk"] if traffic else None},
         "roofline_pass": {"bound": "alu",
-                          "kernel": "counting pass: k_bin_classify + k_bin_scan_blocks + "
+                          "kernel": "counting pass: k_bin_classify + k_bin_scan_groups + k_bin_scan_sums + "
                                     "k_bin_plan + k_bin_scatter + k_item_setup + k_walk_tiles + "
                                     "k_reduce_tiles + k_walk_overflow, one hull_all call",
                           "per_unit": "6 int32 lane-ops per voxel visit", "units": visits,

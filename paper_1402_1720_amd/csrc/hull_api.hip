@@ -244,7 +244,11 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t B, void *base, size_t *bytes)
     w.oq = reinterpret_cast<int32_t *>(take((size_t)B * 24));
     w.meta = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
     w.lpack = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
+    w.ngroups = (w.nblk + kScanGroup - 1) / kScanGroup;
     w.blk = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.nblk * 4));
+    w.boff = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.nblk * 4));
+    w.gsum = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.ngroups * 4));
+    w.goff = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.ngroups * 4));
     w.sub_total = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * 4));
     w.sub_start = reinterpret_cast<uint32_t *>(take((size_t)(w.nsub + 1) * 4));
     w.tile_start = reinterpret_cast<uint32_t *>(take((size_t)(w.ntiles + 1) * 4));
@@ -380,6 +384,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         const int64_t nb = std::min<int64_t>(w.B, h->n - h0);
         BinWs wb = w;
         wb.nblk = (int)((nb + kHistPerBlock - 1) / kHistPerBlock);
+        wb.ngroups = (wb.nblk + kScanGroup - 1) / kScanGroup;
         wb.min_ranges = rpg * walk_grid;
         wb.run_stride = o.run_stride > 0 ? o.run_stride : default_run_stride(wb.nblk);
         mark(HULL_PROF_CLASSIFY);
@@ -387,7 +392,8 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
                                                        M != nullptr, tile_ok ? 1 : 0, wb, stats);
         done();
         mark(HULL_PROF_SCAN);
-        k_bin_scan_blocks<<<wb.nsub, 256, (size_t)(wb.nblk + wb.nblk / 32 + 1) * 4, s>>>(wb);
+        k_bin_scan_groups<<<wb.ngroups, 256, 0, s>>>(wb);
+        k_bin_scan_sums<<<(wb.nsub + 3) / 4, 256, 0, s>>>(wb);
         done();
         mark(HULL_PROF_PLAN);
         k_bin_plan<<<1, 1024, 0, s>>>(wb);

@@ -20,6 +20,7 @@ constexpr int kHistPerThread = 32;
 constexpr int kHistPerBlock = kBinThreads * kHistPerThread;
 constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic walk
 constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
+constexpr int kScanGroup = 16;         // block columns per first-step scan group
 constexpr int kTileThreads = 1024;      // workgroup of the LDS walk
 static_assert(kTileThreads % 256 == 0, "the walk deals items in groups of four waves");
 constexpr int kItemsPerRange = 65535;   // a range holds at most this many items: each adds
@@ -51,7 +52,10 @@ struct BinWs {
     int32_t *oq;            // [B][6] quantised endpoints of the lines the global walk takes
     uint32_t *meta;         // per history
     uint32_t *lpack;        // per history: 4-bit length class per slice
-    uint32_t *blk;          // [nsub][nblk] counts, then offsets
+    uint32_t *blk;          // [nblk][nsub] items of each (block column, sub-bin)
+    uint32_t *boff;         // [nblk][nsub] offset of a column within its scan group
+    uint32_t *gsum;         // [nsub][ngroups] items per (sub-bin, scan group)
+    uint32_t *goff;         // [ngroups][nsub] offset of a scan group within its sub-bin
     uint32_t *sub_total;    // [nsub]
     uint32_t *sub_start;    // [nsub + 1]
     uint32_t *tile_start;   // [ntiles + 1]
@@ -65,7 +69,7 @@ struct BinWs {
                             // history of an overflow item
     uint32_t *partial;      // [max_slots][slot_words]
     int nz, nl, lwidth;     // slices, length classes per slice, class width (voxels)
-    int nsub, ntiles, nblk, tile_words, max_ranges, max_slots, min_ranges;
+    int nsub, ntiles, nblk, ngroups, tile_words, max_ranges, max_slots, min_ranges;
     int slot_words;         // tile_words rounded up to a multiple of four
     int stride, gnx, gny;   // tile row length in counters (odd), grid columns and rows
     int run_stride;         // runs of a sub-bin ordered by block modulo this
@@ -75,7 +79,8 @@ struct BinWs {
 __global__ void k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_low,
                                float e_high, int use_low, int use_high, int tile_ok, BinWs w,
                                hullmi_stats *st);
-__global__ void k_bin_scan_blocks(BinWs w);
+__global__ void k_bin_scan_groups(BinWs w);
+__global__ void k_bin_scan_sums(BinWs w);
 __global__ void k_bin_plan(BinWs w);
 __global__ void k_bin_scatter(int64_t nb, BinWs w);
 __global__ void k_item_setup(BinWs w, int nx, int ny);

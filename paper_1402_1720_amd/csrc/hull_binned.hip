@@ -260,7 +260,7 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
     __syncthreads();
     const int col = blk_col((int)blockIdx.x, w.nblk, w.run_stride);
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
-        w.blk[(int64_t)b * w.nblk + col] = lh[b];
+        w.blk[(int64_t)col * w.nsub + b] = lh[b];
     if (st) {
         unsigned long long v;
         v = block_sum(nl, red);  if (threadIdx.x == 0) add_stats(st, 0, v);
@@ -312,26 +312,53 @@ __device__ T block_exclusive_scan(int n, Get get, T *out, T *sh)
     return block_exclusive_scan_to<T>(n, get, [&](int i, T v) { out[i] = v; }, sh);
 }
 
-// One block per sub-bin: exclusive scan of its per-block counts, in place.
-// The row is staged in LDS with coalesced loads, scanned there (each thread a
-// contiguous chunk, then wave shuffles over the chunk sums) and written back
-// coalesced. One pad word after every 32 puts the chunks of a wave's lanes,
-// 32 words each for 8192 blocks, in different LDS banks.
-__device__ __forceinline__ int scan_slot(int i) { return i + (i >> 5); }
-
-__global__ void __launch_bounds__(256) k_bin_scan_blocks(BinWs w)
+// The per-block counts are a matrix of block columns (rows, in run order) by
+// sub-bins, so that a classification block writes, and a scatter block
+// reads, one contiguous row. Each sub-bin's exclusive scan over the columns
+// runs in two steps: within groups of kScanGroup columns (a thread per
+// sub-bin, reading down its column, a wave reading 64 neighbouring sub-bins
+// of a row at a time), then over the group sums.
+__global__ void __launch_bounds__(256) k_bin_scan_groups(BinWs w)
 {
-    extern __shared__ uint32_t rowl[];   // [scan_slot(nblk)]
-    __shared__ uint32_t sh[5];
-    uint32_t *row = w.blk + (int64_t)blockIdx.x * w.nblk;
-    const int n = w.nblk;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) rowl[scan_slot(i)] = row[i];
-    __syncthreads();
-    const uint32_t total = block_exclusive_scan_to<uint32_t>(
-        n, [&](int i) { return rowl[scan_slot(i)]; },
-        [&](int i, uint32_t v) { rowl[scan_slot(i)] = v; }, sh);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = rowl[scan_slot(i)];
-    if (threadIdx.x == 0) w.sub_total[blockIdx.x] = total;
+    const int g = blockIdx.x;
+    const int c0 = g * kScanGroup;
+    const int nc = min(kScanGroup, w.nblk - c0);
+    for (int s = threadIdx.x; s < w.nsub; s += blockDim.x) {
+        uint32_t v[kScanGroup];
+#pragma unroll
+        for (int i = 0; i < kScanGroup; ++i)
+            v[i] = i < nc ? w.blk[(int64_t)(c0 + i) * w.nsub + s] : 0u;
+        uint32_t acc = 0;
+#pragma unroll
+        for (int i = 0; i < kScanGroup; ++i) {
+            if (i < nc) w.boff[(int64_t)(c0 + i) * w.nsub + s] = acc;
+            acc += v[i];
+        }
+        w.gsum[(int64_t)s * w.ngroups + g] = acc;
+    }
+}
+
+// One wave per sub-bin: exclusive scan of its group sums, 64 groups at a
+// time; the group offsets are written group-major (a scatter block reads its
+// group's row), the total per sub-bin beside them.
+__global__ void __launch_bounds__(256) k_bin_scan_sums(BinWs w)
+{
+    const int s = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (s >= w.nsub) return;   // whole waves
+    const int lane = threadIdx.x & 63;
+    uint32_t carry = 0;
+    for (int g0 = 0; g0 < w.ngroups; g0 += 64) {
+        const int g = g0 + lane;
+        const uint32_t v = g < w.ngroups ? w.gsum[(int64_t)s * w.ngroups + g] : 0u;
+        uint32_t inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (g < w.ngroups) w.goff[(int64_t)g * w.nsub + s] = carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) w.sub_total[s] = carry;
 }
 
 __device__ __forceinline__ unsigned long long item_work(const BinWs &w, int sub)
@@ -411,8 +438,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
 {
     __shared__ uint32_t cur[kMaxSubBins];
     const int col = blk_col((int)blockIdx.x, w.nblk, w.run_stride);
+    const int64_t row = (int64_t)col * w.nsub, grow = (int64_t)(col / kScanGroup) * w.nsub;
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
-        cur[b] = w.sub_start[b] + w.blk[(int64_t)b * w.nblk + col];
+        cur[b] = w.sub_start[b] + w.goff[grow + b] + w.boff[row + b];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kHistPerBlock + threadIdx.x;
     // the next history's meta word, length classes and packed record are

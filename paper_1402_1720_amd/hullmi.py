@@ -365,7 +365,8 @@ def hull_all(hist: Histories, grid, params: hullmi_params, N: torch.Tensor, M: t
 # hull_prof_kernel entries: counting pass, then the FDK hull
 PROF_KERNELS = ("classify", "scan", "plan", "scatter", "setup", "walk", "reduce", "overflow",
                 "fbp_clear", "fbp_bin", "fbp_filter", "fbp_geometry", "fbp_backproject")
-PROF_KERNEL_NAMES = ("k_bin_classify", "k_bin_scan_blocks", "k_bin_plan", "k_bin_scatter",
+PROF_KERNEL_NAMES = ("k_bin_classify", "k_bin_scan_groups + k_bin_scan_sums", "k_bin_plan",
+                     "k_bin_scatter",
                      "k_item_setup", "k_walk_tiles", "k_reduce_tiles", "k_walk_overflow",
                      "k_fill_u64 + k_fill_u32", "k_fbp_bin_lds", "k_fill_u32 + k_fbp_filter",
                      "k_fbp_trig + k_fbp_footprint", "k_fbp_backproject_tiles")
