@@ -399,7 +399,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         k_bin_plan<<<1, 1024, 0, s>>>(wb);
         done();
         mark(HULL_PROF_SCATTER);
-        k_bin_scatter<<<wb.nblk, kBinThreads, 0, s>>>(nb, wb);
+        k_bin_scatter<<<wb.nblk, kScatterThreads, 0, s>>>(nb, wb);
         done();
         if (tile_ok) {
             // 16 blocks per CU: 125 us against 131 us with 8 and 153 us with 4

@@ -15,9 +15,10 @@
 
 namespace hullmi {
 
-constexpr int kBinThreads = 256;        // classify / scatter block
+constexpr int kBinThreads = 256;        // classify block
 constexpr int kHistPerThread = 32;
 constexpr int kHistPerBlock = kBinThreads * kHistPerThread;
+constexpr int kScatterThreads = 1024;   // scatter block: the same 8192 histories
 constexpr int kMaxSlicesPerLine = 6;    // longer lines go to the global-atomic walk
 constexpr int kMaxSubBins = 4098;       // LDS histogram of the classify / scatter blocks
 constexpr int kScanGroup = 16;         // block columns per first-step scan group

@@ -434,7 +434,13 @@ __global__ void __launch_bounds__(1024) k_bin_plan(BinWs w)
     }
 }
 
-__global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w)
+// Writes the items of one classification block (8192 histories) to their
+// runs: an LDS cursor per sub-bin, started at where this block's run of the
+// sub-bin begins. A thread takes eight histories and loads all of their meta
+// words, length classes and packed records before it stores anything: vector
+// memory operations retire in order, so a load issued after a scattered store
+// would wait for that store, and the stores would set the pace.
+__global__ void __launch_bounds__(kScatterThreads) k_bin_scatter(int64_t nb, BinWs w)
 {
     __shared__ uint32_t cur[kMaxSubBins];
     const int col = blk_col((int)blockIdx.x, w.nblk, w.run_stride);
@@ -442,43 +448,35 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(int64_t nb, BinWs w
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x)
         cur[b] = w.sub_start[b] + w.goff[grow + b] + w.boff[row + b];
     __syncthreads();
+    constexpr int R = kHistPerBlock / kScatterThreads;
     const int64_t base = (int64_t)blockIdx.x * kHistPerBlock + threadIdx.x;
-    // the next history's meta word, length classes and packed record are
-    // loaded (independently of each other) while the current one is placed;
-    // the record of an unclassified history is read but not used
-    struct Next { uint32_t m, lp; uint4 rec; };
-    auto fetch = [&](int r, Next &x) {
-        const int64_t j = base + (int64_t)r * kBinThreads;
-        x.m = 0;
-        if (r < kHistPerThread && j < nb) {
-            x.m = w.meta[j];
-            x.lp = w.lpack[j];
-            x.rec = w.hrec[j];
-        }
-    };
-    Next nxt;
-    fetch(0, nxt);
-    for (int r = 0; r < kHistPerThread; ++r) {
-        if (base + (int64_t)r * kBinThreads >= nb) break;
-        const Next cu = nxt;
-        fetch(r + 1, nxt);
-        const uint32_t m = cu.m;
-        if (!(m & kMetaValid)) continue;
-        const int cls = (m & kMetaHigh) ? 1 : 0;
-        if (m & kMetaOverflow) {
+    uint32_t m[R], lp[R];
+    uint4 rec[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = base + (int64_t)r * kScatterThreads;
+        m[r] = j < nb ? w.meta[j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = base + (int64_t)r * kScatterThreads;
+        // the record of an unclassified history is read but not used
+        lp[r] = j < nb ? w.lpack[j] : 0u;
+        rec[r] = j < nb ? w.hrec[j] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!(m[r] & kMetaValid)) continue;
+        const int cls = (m[r] & kMetaHigh) ? 1 : 0;
+        if (m[r] & kMetaOverflow) {
             // the overflow walk reads the full record by history
-            const uint32_t j = (uint32_t)(base + (int64_t)r * kBinThreads);
+            const uint32_t j = (uint32_t)(base + (int64_t)r * kScatterThreads);
             w.item[atomicAdd(&cur[w.nsub - 2 + cls], 1u)] = make_uint4(j, 0u, 0u, 0u);
         } else {
-            const int k0 = (int)(m & 0xfffu), ns = (int)((m >> 12) & 0xfffu);
+            const int k0 = (int)(m[r] & 0xfffu), ns = (int)((m[r] >> 12) & 0xfffu);
             for (int k = k0; k < k0 + ns; ++k) {
-                const int lc = (int)((cu.lp >> (4 * (k - k0))) & 0xfu);
-                // two 8-byte stores: scattered 16-byte stores took twice as
-                // long here (188 vs 367 us for 1.1e7 items)
-                uint2 *dst = reinterpret_cast<uint2 *>(
-                    w.item + atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u));
-                dst[0] = make_uint2(cu.rec.x, cu.rec.y);
-                dst[1] = make_uint2(cu.rec.z, cu.rec.w);
+                const int lc = (int)((lp[r] >> (4 * (k - k0))) & 0xfu);
+                w.item[atomicAdd(&cur[(cls * w.nz + k) * w.nl + lc], 1u)] = rec[r];
             }
         }
     }
