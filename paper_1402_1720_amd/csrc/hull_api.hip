@@ -240,10 +240,10 @@ BinWs bin_ws_layout(const hullmi_grid *g, int64_t B, void *base, size_t *bytes)
         off += align_up(nbytes);
         return p;
     };
-    w.hrec = reinterpret_cast<uint4 *>(take((size_t)B * 16));
-    w.oq = reinterpret_cast<int32_t *>(take((size_t)B * 24));
-    w.meta = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
-    w.lpack = reinterpret_cast<uint32_t *>(take((size_t)B * 4));
+    const size_t Bp = (size_t)w.nblk * kHistPerBlock;   // whole classification blocks
+    w.hrec = reinterpret_cast<uint4 *>(take(Bp * 16));
+    w.meta = reinterpret_cast<uint32_t *>(take(Bp * 4));
+    w.lpack = reinterpret_cast<uint32_t *>(take(Bp * 4));
     w.ngroups = (w.nblk + kScanGroup - 1) / kScanGroup;
     w.blk = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.nblk * 4));
     w.boff = reinterpret_cast<uint32_t *>(take((size_t)w.nsub * w.nblk * 4));
@@ -416,7 +416,7 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
             done();
         }
         mark(HULL_PROF_OVERFLOW);
-        k_walk_overflow<<<1024, 256, 0, s>>>(wb, g->nx, g->ny, g->nz, N, M, stats);
+        k_walk_overflow<<<1024, 256, 0, s>>>(*h, h0, dg, wb, N, M, stats);
         done();
         const int rc = launch_status();
         if (rc != HULL_OK) return rc;

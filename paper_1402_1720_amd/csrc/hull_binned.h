@@ -49,8 +49,8 @@ enum : int { kCtlRanges = 0, kCtlItems = 1, kCtlOverflowStart = 2, kCtlOverflowC
 constexpr int kPackLimit = 1 << 20;
 
 struct BinWs {
-    uint4 *hrec;            // [B] per history: the packed endpoints of a tile line, else zeros
-    int32_t *oq;            // [B][6] quantised endpoints of the lines the global walk takes
+    // per-history arrays hold whole classification blocks (B rounded up)
+    uint4 *hrec;            // per history: the packed endpoints of a tile line, else zeros
     uint32_t *meta;         // per history
     uint32_t *lpack;        // per history: 4-bit length class per slice
     uint32_t *blk;          // [nblk][nsub] items of each (block column, sub-bin)
@@ -87,6 +87,7 @@ __global__ void k_bin_scatter(int64_t nb, BinWs w);
 __global__ void k_item_setup(BinWs w, int nx, int ny);
 __global__ void k_walk_tiles(BinWs w, int nx, int ny);
 __global__ void k_reduce_tiles(BinWs w, int plane, int *N, int *M, hullmi_stats *st);
-__global__ void k_walk_overflow(BinWs w, int nx, int ny, int nz, int *N, int *M, hullmi_stats *st);
+__global__ void k_walk_overflow(hullmi_histories h, int64_t h0, DevGrid g, BinWs w, int *N,
+                                int *M, hullmi_stats *st);
 
 }  // namespace hullmi

@@ -135,6 +135,39 @@ __device__ __forceinline__ int length_class(const LineSlab &b, float rdz, int k,
     return c > 0.0f ? (int)c : 0;
 }
 
+// Quantised endpoints of history i (batch-relative index into h, whose
+// arrays start at h0): kGeoOk or the reason the history is skipped. c, s and
+// bits cache the cosine and sine of the last angle seen (histories come in
+// long runs of one gantry angle, and equal angle bits give equal c, s).
+__device__ __forceinline__ int history_line(float xi, float yi, float zi, float xo, float yo,
+                                            float zo, float a, const DevGrid &g, uint32_t &bits,
+                                            float &c, float &s, int q[6])
+{
+    int st = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) && isfinite(yo) &&
+              isfinite(zo) && isfinite(a))
+                 ? kGeoOk
+                 : kGeoNonFinite;
+    if (st == kGeoOk) {
+        if (__float_as_uint(a) != bits) {
+            deg_cos_sin(a, c, s);
+            bits = __float_as_uint(a);
+        }
+        st = quantize_point(c, s, xi, yi, zi, g, q[0], q[1], q[2]);
+        if (st == kGeoOk) st = quantize_point(c, s, xo, yo, zo, g, q[3], q[4], q[5]);
+        if (st == kGeoOk && q[0] == q[3] && q[1] == q[4] && q[2] == q[5]) st = kGeoDegenerate;
+    }
+    return st;
+}
+
+// Every lane loads every field of every history of its block, in range or
+// not (an index past the batch is clamped to its last history, and what a
+// lane computes there is dropped), and stores its three words for each
+// (the per-history arrays are padded to whole blocks): with no memory
+// operation under a lane-dependent condition the compiler counts the loads in
+// flight exactly, and a history's loads no longer wait for the previous
+// history's stores. A wave's 64 consecutive histories share the cache lines
+// of every field, so loading the geometry of the histories outside the
+// counted classes costs little traffic.
 __global__ void __launch_bounds__(kBinThreads)
 k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_low, float e_high,
                int use_low, int use_high, int tile_ok, BinWs w, hullmi_stats *st)
@@ -144,68 +177,41 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
     for (int b = threadIdx.x; b < w.nsub; b += blockDim.x) lh[b] = 0;
     __syncthreads();
     unsigned long long nl = 0, nh = 0, nsk = 0, nmi = 0;
-    // cosine and sine of the last angle seen by this thread: histories come
-    // in long runs of one gantry angle, and equal angle bits give equal c, s
     uint32_t trig_bits = 0x7fc00001u;   // a NaN: finite angles never match it
     float tc = 1.0f, ts = 0.0f;
     const int64_t base = (int64_t)blockIdx.x * kHistPerBlock;
-    // two-stage prefetch: the WEPL two histories ahead, and the geometry of the
-    // next history when its WEPL puts it in a class being counted (a wave with
-    // no such lane skips those loads)
-    auto in_class = [&](float wv) {
-        return isfinite(wv) && ((use_low && wv < e_low) || (use_high && wv > e_high));
-    };
     auto hist_at = [&](int r) { return base + (int64_t)r * kBinThreads + threadIdx.x; };
-    struct Geo { float xi, yi, zi, xo, yo, zo, a; };
-    auto fetch_geo = [&](int64_t i, Geo &f) {
+    auto src = [&](int r) { return h0 + min(hist_at(r), nb - 1); };
+    struct Geo { float xi, yi, zi, xo, yo, zo, a, wv; };
+    auto fetch = [&](int64_t i, Geo &f) {
         f.xi = h.x_in[i]; f.yi = h.y_in[i]; f.zi = h.z_in[i];
         f.xo = h.x_out[i]; f.yo = h.y_out[i]; f.zo = h.z_out[i]; f.a = h.angle_deg[i];
+        f.wv = h.wepl[i];
     };
-    float w_next = 0.0f, w_next2 = 0.0f;
-    Geo g_next{};
-    if (hist_at(0) < nb) {
-        w_next = h.wepl[h0 + hist_at(0)];
-        if (in_class(w_next)) fetch_geo(h0 + hist_at(0), g_next);
-    }
-    if (kHistPerThread > 1 && hist_at(1) < nb) w_next2 = h.wepl[h0 + hist_at(1)];
+    // the next history's fields are in flight while the current one is classified
+    Geo nxt;
+    fetch(src(0), nxt);
     for (int r = 0; r < kHistPerThread; ++r) {
         const int64_t j = hist_at(r);
-        if (j >= nb) break;
-        const float wv = w_next;
-        const Geo cf = g_next;
-        w_next = w_next2;
-        if (r + 1 < kHistPerThread && hist_at(r + 1) < nb && in_class(w_next))
-            fetch_geo(h0 + hist_at(r + 1), g_next);
-        if (r + 2 < kHistPerThread && hist_at(r + 2) < nb) w_next2 = h.wepl[h0 + hist_at(r + 2)];
+        const bool live = j < nb;
+        const Geo cf = nxt;
+        fetch(src(r + 1 < kHistPerThread ? r + 1 : r), nxt);
+        const float wv = cf.wv;
         uint32_t meta = 0;
         // every history's record and length word is written (zeros when
         // unused), so that the block writes whole cache lines
-        int q[6];
         uint4 rec = make_uint4(0u, 0u, 0u, 0u);
         uint32_t lp = 0;
-        if (!isfinite(wv)) {
+        if (!live) {
+        } else if (!isfinite(wv)) {
             ++nsk;
         } else {
             const bool low = use_low && wv < e_low;
             const bool high = use_high && wv > e_high;
             if (low || high) {
-                const float xi = cf.xi, yi = cf.yi, zi = cf.zi;
-                const float xo = cf.xo, yo = cf.yo, zo = cf.zo;
-                const float a = cf.a;
-                int stg = (isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(xo) &&
-                           isfinite(yo) && isfinite(zo) && isfinite(a))
-                              ? kGeoOk
-                              : kGeoNonFinite;
-                if (stg == kGeoOk) {
-                    if (__float_as_uint(a) != trig_bits) {
-                        deg_cos_sin(a, tc, ts);
-                        trig_bits = __float_as_uint(a);
-                    }
-                    stg = quantize_point(tc, ts, xi, yi, zi, g, q[0], q[1], q[2]);
-                    if (stg == kGeoOk) stg = quantize_point(tc, ts, xo, yo, zo, g, q[3], q[4], q[5]);
-                    if (stg == kGeoOk && q[0] == q[3] && q[1] == q[4] && q[2] == q[5])
-                        stg = kGeoDegenerate;
-                }
+                int q[6];
+                const int stg = history_line(cf.xi, cf.yi, cf.zi, cf.xo, cf.yo, cf.zo, cf.a, g,
+                                             trig_bits, tc, ts, q);
                 if (stg != kGeoOk) {
                     ++nsk;
                 } else {
@@ -233,12 +239,9 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                         bool packs = true;
                         for (int c = 0; c < 6; ++c) packs &= q[c] >= -kPackLimit && q[c] < kPackLimit;
                         if (!tile_ok || ns > kMaxSlicesPerLine || wide || !packs) {
+                            // the global walk quantises the history again
                             meta |= kMetaOverflow;
                             atomicAdd(&lh[w.nsub - 2 + cls], 1u);
-                            int2 *o = reinterpret_cast<int2 *>(w.oq + 6 * j);
-                            o[0] = make_int2(q[0], q[1]);
-                            o[1] = make_int2(q[2], q[3]);
-                            o[2] = make_int2(q[4], q[5]);
                         } else {
                             rec = pack_line(q);
                             const float rdz = sb.d[2] != 0.0f ? __builtin_amdgcn_rcpf(sb.d[2]) : 0.0f;
@@ -687,19 +690,27 @@ struct GlobalAcc3 {
 };
 
 // Lines listed in the overflow bins, walked through the whole grid with global
-// atomics (grid-stride over a count known only on the device).
+// atomics (grid-stride over a count known only on the device); each line is
+// quantised again from its history, as classification did.
 __global__ void __launch_bounds__(256)
-k_walk_overflow(BinWs w, int nx, int ny, int nz, int *N, int *M, hullmi_stats *st)
+k_walk_overflow(hullmi_histories h, int64_t h0, DevGrid g, BinWs w, int *N, int *M,
+                hullmi_stats *st)
 {
     __shared__ unsigned long long red[16];
     const int start = w.ctl[kCtlOverflowStart], count = w.ctl[kCtlOverflowCount];
     const int nlow = w.ctl[kCtlOverflowLow];
     unsigned long long vl = 0, vh = 0;
+    uint32_t trig_bits = 0x7fc00001u;
+    float tc = 1.0f, ts = 0.0f;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        const int32_t *q = w.oq + 6 * (size_t)w.item[start + t].x;
+        const int64_t i = h0 + w.item[start + t].x;
+        int q[6];
+        // classification listed the line, so its quantisation succeeds
+        history_line(h.x_in[i], h.y_in[i], h.z_in[i], h.x_out[i], h.y_out[i], h.z_out[i],
+                     h.angle_deg[i], g, trig_bits, tc, ts, q);
         const bool high = t >= nlow;
         GlobalAcc3 acc{high ? M : N};
-        const int v = walk_line(q[0], q[1], q[2], q[3], q[4], q[5], nx, ny, nz, acc);
+        const int v = walk_line(q[0], q[1], q[2], q[3], q[4], q[5], g.nx, g.ny, g.nz, acc);
         if (high) vh += (unsigned long long)v; else vl += (unsigned long long)v;
     }
     if (st) {
