@@ -134,8 +134,32 @@ __device__ __forceinline__ int carve_slice(int a0, int a1, int a2, int b0, int b
         oy = f.sy * nx;
         d = f.dxy;
     }
+    // Both steps change d by a multiple of 2048 (incx = 2048 Ay, incy = -2048
+    // Ax), so d = 2048 q + r with r = d mod 2048 fixed for the line: d < 0
+    // exactly when q < 0, and d = 0 exactly when q = 0 and r = 0. The walk
+    // keeps q, in 32 bits (|q| <= Ax + Ay + 1 < 2^23), and a line with r != 0
+    // never takes a corner step.
+    int32_t q = (int32_t)(d >> 11);
+    const bool ties = (d & 2047) == 0;
+    const int32_t ax = (int32_t)(-incy >> 11), ay = (int32_t)(incx >> 11);
     const int64_t sl = (int64_t)k * nx * ny;
+    const bool all_in = sl - wbase >= 0 && sl + (int64_t)nx * ny - wbase <= wbits;
     int cnt = 0;
+    if (all_in && !ties) {
+        // the slice lies inside the LDS window and the line has no corner step
+        unsigned *ws = win + ((sl - wbase) >> 5);
+        const int sh = (int)((sl - wbase) & 31);   // 0: the window starts on a word
+        for (int it = nx + ny; it > 0; --it) {
+            const int rel = off + sh;
+            atomicOr(ws + (rel >> 5), 1u << (rel & 31));
+            ++cnt;
+            if (off == last) break;
+            const bool bx = q < 0;
+            q += bx ? ay : -ax;
+            off += bx ? ox : oy;
+        }
+        return cnt;
+    }
     for (int it = nx + ny; it > 0; --it) {
         const int64_t gi = sl + off, rel = gi - wbase;
         if ((uint64_t)rel < (uint64_t)wbits)
@@ -144,8 +168,8 @@ __device__ __forceinline__ int carve_slice(int a0, int a1, int a2, int b0, int b
             atomicOr(gbits + (gi >> 5), 1u << (gi & 31));
         ++cnt;
         if (off == last) break;
-        const bool tie = d == 0, bx = d < 0;
-        d += tie ? incx + incy : (bx ? incx : incy);
+        const bool tie = ties && q == 0, bx = q < 0;
+        q += tie ? ay - ax : (bx ? ay : -ax);
         off += tie ? ox + oy : (bx ? ox : oy);
     }
     return cnt;
