@@ -586,9 +586,24 @@ __global__ void __launch_bounds__(kTileThreads) k_walk_tiles(BinWs w, int nx, in
                 // the first step adds to the half of the first counter's word
                 const uint32_t val = (off & 2) ? 65536u : 1u;
                 if (__all(!live || (a.z & kStateNoCorner))) {
-                    if (live)
-                        walk_slice_lds16_nocorner((int32_t)a.x, off, last, incx, incy, ox, oy, val,
-                                                  nx + ny);
+                    if (live) {
+                        // word-address increments of x and y steps from the starting
+                        // half (first steps of a round) and from the other half
+                        // (second steps): counter L + sx or L + sy S (S odd) against
+                        // word L >> 1
+                        const int32_t p0 = (off >> 1) & 1;
+                        const int32_t S = w.stride;
+                        const bool xp = ox > 0, yp = oy > 0;
+                        auto dx = [&](int32_t p) { return xp ? (p ? 4 : 0) : (p ? 0 : -4); };
+                        auto dy = [&](int32_t p) {
+                            return yp ? (p ? 2 * (S + 1) : 2 * (S - 1)) : (p ? -2 * (S - 1) : -2 * (S + 1));
+                        };
+                        const bool last_first = (((last >> 1) & 1) == p0);
+                        const int32_t lw = last & ~3;
+                        walk_slice_lds16_nocorner_w((int32_t)a.x, off & ~3, last_first ? lw : -1,
+                                                    last_first ? -1 : lw, incx, incy, dx(p0), dy(p0),
+                                                    dx(1 - p0), dy(1 - p0), val, nx + ny);
+                    }
                 } else if (live) {
                     walk_slice_lds16((int32_t)a.x, off, last, incx, incy, ox, oy, val, nx + ny);
                 }

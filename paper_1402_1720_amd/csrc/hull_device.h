@@ -320,6 +320,68 @@ __device__ __forceinline__ void walk_slice_lds16_nocorner(int32_t d, int32_t off
         : "scc", "memory");
 }
 
+// walk_slice_lds16_nocorner on word addresses. Every step of a corner-free
+// line moves its counter to the other half of a word, so the first step of
+// each round is always on the half the line starts on and the second on the
+// other one: the word-address change of an x step and of a y step at each of
+// the two positions is fixed for the line (dxa, dya for the first, dxb, dyb
+// for the second), and the loop keeps the word address itself instead of
+// masking a counter address at every step. The last voxel is reached at a
+// first step when its half is the starting half, else at a second step, so
+// each position compares with the last voxel's word only where it can be
+// reached (last_a, last_b; -1 where it cannot, which no word address equals;
+// a line visits each voxel once, so a match at that position is the last
+// voxel). The same voxels in the same order; 6 VALU instructions and one
+// ds_add_u32 per step.
+__device__ __forceinline__ void walk_slice_lds16_nocorner_w(int32_t d, int32_t w, int32_t last_a,
+                                                            int32_t last_b, int32_t incx,
+                                                            int32_t incy, int32_t dxa,
+                                                            int32_t dya, int32_t dxb, int32_t dyb,
+                                                            uint32_t val, int32_t maxit)
+{
+    const uint32_t val2 = val ^ 65537u;
+    int32_t t2, t3, w2;
+    uint64_t save, sbx, sdone;
+    int32_t it = (maxit + 1) >> 1;
+    // the two steps of a round keep the word address in alternate registers
+    // (w, then w2), so no register is written right after a ds_add_u32 that
+    // reads it
+    asm volatile(
+        "s_mov_b64 %[save], exec\n"
+        "1:\n"
+        // compares first: every SGPR a VALU writes is read at least three
+        // instructions later
+        "v_cmp_gt_i32 %[sbx], 0, %[d]\n"
+        "v_cmp_ne_u32 %[sdone], %[w], %[la]\n"
+        "ds_add_u32 %[w], %[val]\n"
+        "v_cndmask_b32 %[t2], %[incy], %[incx], %[sbx]\n"
+        "v_cndmask_b32 %[t3], %[dya], %[dxa], %[sbx]\n"
+        "v_add_u32 %[d], %[d], %[t2]\n"
+        "v_add_u32 %[w2], %[w], %[t3]\n"
+        "s_and_b64 exec, exec, %[sdone]\n"
+        "s_cbranch_execz 2f\n"
+        "v_cmp_gt_i32 %[sbx], 0, %[d]\n"
+        "v_cmp_ne_u32 %[sdone], %[w2], %[lb]\n"
+        "ds_add_u32 %[w2], %[val2]\n"
+        "v_cndmask_b32 %[t2], %[incy], %[incx], %[sbx]\n"
+        "v_cndmask_b32 %[t3], %[dyb], %[dxb], %[sbx]\n"
+        "v_add_u32 %[d], %[d], %[t2]\n"
+        "v_add_u32 %[w], %[w2], %[t3]\n"
+        "s_and_b64 exec, exec, %[sdone]\n"
+        "s_cbranch_execz 2f\n"
+        "s_sub_u32 %[it], %[it], 1\n"
+        "s_cmp_eq_u32 %[it], 0\n"
+        "s_cbranch_scc0 1b\n"
+        "2:\n"
+        "s_mov_b64 exec, %[save]\n"
+        : [d] "+v"(d), [w] "+v"(w), [it] "+s"(it), [t2] "=&v"(t2), [t3] "=&v"(t3),
+          [w2] "=&v"(w2), [save] "=&s"(save), [sbx] "=&s"(sbx), [sdone] "=&s"(sdone)
+        : [la] "v"(last_a), [lb] "v"(last_b), [incx] "v"(incx), [incy] "v"(incy),
+          [dxa] "v"(dxa), [dya] "v"(dya), [dxb] "v"(dxb), [dyb] "v"(dyb), [val] "v"(val),
+          [val2] "v"(val2)
+        : "scc", "memory");
+}
+
 // Whether the line's projection on the x-y plane passes through no voxel
 // corner (no point with both coordinates multiples of kQ): a corner
 // (kQ i, kQ j) on P + t D needs kQ (Dy i - Dx j) = Dy Px - Dx Py, so it
