@@ -88,18 +88,22 @@ def cpu_model():
     return "unknown"
 
 
-def timed_on(torch, stream, fn, reps):
+def timed_on(torch, stream, fn, reps, groups=3):
     """Mean ms of `reps` calls of fn between two events on `stream` (one
-    untimed call first)."""
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    untimed call first), the median over `groups` such groups, so that one
+    group disturbed by the host does not set the figure."""
     fn()
     torch.cuda.synchronize()
-    a.record(stream)
-    for _ in range(reps):
-        fn()
-    b.record(stream)
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+    means = []
+    for _ in range(groups):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        means.append(a.elapsed_time(b) / reps)
+    return float(np.median(means))
 
 
 def to_device(torch, gen, spec, dev, step=20_000_000):
