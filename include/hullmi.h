@@ -40,6 +40,14 @@
  *     and return without waiting. They allocate no device memory: the
  *     workspace is passed in, sized by hull_workspace_bytes(). Calls on
  *     different streams with disjoint outputs and workspaces may overlap.
+ *   - hull_sc, hull_msc, hull_sm and hull_all may also run part of their
+ *     work on a second stream that the library creates once per device
+ *     (non-blocking, default priority, kept until the process ends): when
+ *     the histories need more than one internal batch of the workspace (see
+ *     hull_workspace_bytes), unless `stream` is being captured into a graph.
+ *     That work starts after everything enqueued on `stream` before the call
+ *     and is joined back into `stream` before the call's last work on it, so
+ *     the call is ordered on `stream` as if it ran there alone.
  *
  * Errors
  *   - Argument errors return HULL_EINVAL before anything is enqueued: a NULL
@@ -173,9 +181,15 @@ const char *hull_strerror(int status);
  * Returns 0 when nothing is needed, or (size_t)-1 on invalid arguments.
  * The counting ops (SC, MSC, SM, ALL) take their histories in internal
  * batches of at most 2^26: this is the size for batches of min(n, 2^26),
- * about 180 bytes per history. They also run in any smaller workspace of at
- * least hull_workspace_bytes(op, grid, min(n, 65536)), in smaller batches
- * (the largest that fit): the same results, with more launches. */
+ * about 150 bytes per history on large scans. They also run in any smaller
+ * workspace of at least hull_workspace_bytes(op, grid, min(n, 65536)), in
+ * smaller batches (the largest that fit): the same results, with more
+ * launches. When the histories need more than one batch of the workspace
+ * passed, the per-scan calls split its counting part in two halves and run
+ * batches of equal size (whole blocks of 8192 histories) that fit a half,
+ * alternately on `stream` and on the library's second stream, so that one
+ * batch's classification and scatter overlap the other's walk; a workspace
+ * whose half cannot hold 65536 histories keeps the batches on `stream`. */
 size_t hull_workspace_bytes(int op, const hullmi_grid *grid, int64_t n,
                             const hullmi_fbp_params *fbp);
 
@@ -309,8 +323,9 @@ enum hull_prof_kernel {
  * pair recorded around every kernel launch on `stream`. Arguments, flags and
  * errors as hull_all (N and M required). The call waits for the stream;
  * then ms[k] (host, HULL_PROF_KERNELS entries) holds the summed duration of
- * kernel k over every internal batch of 2^24 histories and launches[k] (host,
- * may be NULL) the number of its launches. The counts equal hull_all's.
+ * kernel k over every internal batch and launches[k] (host, may be NULL) the
+ * number of its launches. The batches are hull_all's with the same workspace,
+ * run one after another on `stream`. The counts equal hull_all's.
  * HULL_EDEVICE also when an event cannot be created or read. */
 int hull_count_profile(const hullmi_histories *hist, const hullmi_grid *grid,
                        const hullmi_params *params, int32_t *N, int32_t *M, uint32_t flags,

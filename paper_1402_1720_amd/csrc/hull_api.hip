@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "hull_binned.h"
 #include "hull_bsc.h"
@@ -335,9 +336,50 @@ FbpWs fbp_ws_layout(const hullmi_fbp_params *p, const hullmi_grid *g, void *base
     return w;
 }
 
+// The second stream of the two-stream counting pass: one per device, created
+// on first use (non-blocking, default priority) and kept until the process
+// ends. Calls from several host threads may share it: every dependency between
+// it and a caller's stream goes through events recorded before they are waited
+// on, so the shared stream can only add waits, never a cycle.
+constexpr int kMaxDevices = 64;
+
+hipStream_t second_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        streams[dev] = nullptr;
+    }
+    return streams[dev];
+}
+
+// Whether work enqueued on s is being captured into a graph (then the pass
+// stays on s alone); unknown counts as captured.
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return st != hipStreamCaptureStatusNone;
+}
+
 // Zero (unless accumulating) and count: the shared core of every hull call.
 // Histories go through in internal batches, as large as the workspace allows
-// (up to kBatch); counts add up across them.
+// (up to kBatch); counts add up across them. With o.two_streams, a pass that
+// needs several batches splits the workspace in two halves and runs batches
+// of equal size that fit a half, alternately on s and on the second stream:
+// one batch's classification, scatter and set-up then run beside the other's
+// walk. The reduce and the overflow walk add into N and M, so each batch's
+// waits for the previous batch's (an event recorded after them).
 int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, float e_high, int32_t *N,
                int32_t *M, uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes,
                hipStream_t s, const CountOpts &o)
@@ -351,7 +393,39 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
         fill_u64(stats, 0ull, stats ? 6 : 0, s);
     }
     if (h->n == 0) return launch_status();
-    BinWs w = bin_ws_layout(g, B, ws, nullptr);
+    int64_t Bw = B;
+    char *second_half = nullptr;
+    hipStream_t s2 = nullptr;
+    if (o.two_streams && h->n > B && !stream_capturing(s)) {
+        const size_t half = ws_bytes / 2 / kAlign * kAlign;
+        const int64_t B2 = batch_for(g, h->n, half);
+        if (B2 > 0) {
+            const int64_t nbat = (h->n + B2 - 1) / B2;
+            const int64_t even = ((h->n + nbat - 1) / nbat + kHistPerBlock - 1) / kHistPerBlock * kHistPerBlock;
+            Bw = std::min(B2, even);
+            second_half = reinterpret_cast<char *>(ws) + half;
+            if (!o.prof) s2 = second_stream();
+        }
+    }
+    hipEvent_t ev_fork = nullptr, ev_acc = nullptr, ev_join = nullptr;
+    auto drop_events = [&]() {
+        for (hipEvent_t e : {ev_fork, ev_acc, ev_join})
+            if (e) (void)hipEventDestroy(e);
+        ev_fork = ev_acc = ev_join = nullptr;
+    };
+    if (s2) {
+        // the second stream starts after everything enqueued on s so far
+        if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ev_acc, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev_fork, s) != hipSuccess || hipStreamWaitEvent(s2, ev_fork, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            drop_events();
+            s2 = nullptr;   // the same batches, on s alone
+        }
+    }
+    BinWs w = bin_ws_layout(g, Bw, ws, nullptr);
+    BinWs w_second = second_half ? bin_ws_layout(g, Bw, second_half, nullptr) : w;
     const DevProps dp = dev_props();
     const size_t tile_bytes = (size_t)tile_lds_bytes(w.stride, g->ny);   // tile + control words
     const bool tile_ok =
@@ -374,54 +448,81 @@ int run_counts(const hullmi_histories *h, const hullmi_grid *g, float e_low, flo
     auto done = [&]() { if (o.prof) o.prof->end(s); };
     if (o.length_classes > 0 && o.length_classes < w.nl) {
         // fewer sub-bins than the workspace is laid out for
-        w.nl = o.length_classes;
-        w.lwidth = length_width(g, w.nl);
-        w.nsub = w.ntiles * w.nl + 2;
+        for (BinWs *x : {&w, &w_second}) {
+            x->nl = o.length_classes;
+            x->lwidth = length_width(g, x->nl);
+            x->nsub = x->ntiles * x->nl + 2;
+        }
     }
     const DevGrid dg = dev_grid(g);
     const int plane = (int)plane_of(g);
-    for (int64_t h0 = 0; h0 < h->n; h0 += w.B) {
-        const int64_t nb = std::min<int64_t>(w.B, h->n - h0);
-        BinWs wb = w;
+    int rc = HULL_OK;
+    int64_t bi = 0;
+    for (int64_t h0 = 0; h0 < h->n && rc == HULL_OK; h0 += Bw, ++bi) {
+        const int64_t nb = std::min<int64_t>(Bw, h->n - h0);
+        const bool second = (bi & 1) != 0;
+        hipStream_t st = s2 && second ? s2 : s;
+        BinWs wb = second ? w_second : w;
         wb.nblk = (int)((nb + kHistPerBlock - 1) / kHistPerBlock);
         wb.ngroups = (wb.nblk + kScanGroup - 1) / kScanGroup;
         wb.min_ranges = rpg * walk_grid;
         wb.run_stride = o.run_stride > 0 ? o.run_stride : default_run_stride(wb.nblk);
         mark(HULL_PROF_CLASSIFY);
-        k_bin_classify<<<wb.nblk, kBinThreads, 0, s>>>(*h, h0, nb, dg, e_low, e_high, N != nullptr,
+        k_bin_classify<<<wb.nblk, kBinThreads, 0, st>>>(*h, h0, nb, dg, e_low, e_high, N != nullptr,
                                                        M != nullptr, tile_ok ? 1 : 0, wb, stats);
         done();
         mark(HULL_PROF_SCAN);
-        k_bin_scan_groups<<<wb.ngroups, 256, 0, s>>>(wb);
-        k_bin_scan_sums<<<(wb.nsub + 3) / 4, 256, 0, s>>>(wb);
+        k_bin_scan_groups<<<wb.ngroups, 256, 0, st>>>(wb);
+        k_bin_scan_sums<<<(wb.nsub + 3) / 4, 256, 0, st>>>(wb);
         done();
         mark(HULL_PROF_PLAN);
-        k_bin_plan<<<1, 1024, 0, s>>>(wb);
+        k_bin_plan<<<1, 1024, 0, st>>>(wb);
         done();
         mark(HULL_PROF_SCATTER);
-        k_bin_scatter<<<wb.nblk, kScatterThreads, 0, s>>>(nb, wb);
+        k_bin_scatter<<<wb.nblk, kScatterThreads, 0, st>>>(nb, wb);
         done();
         if (tile_ok) {
             // 16 blocks per CU: 125 us against 131 us with 8 and 153 us with 4
             // (1.1e7 items, 200x200x32)
             mark(HULL_PROF_SETUP);
-            k_item_setup<<<dp.cus * 16, 256, (size_t)(wb.ntiles + 1) * 4, s>>>(wb, g->nx, g->ny);
+            k_item_setup<<<dp.cus * 16, 256, (size_t)(wb.ntiles + 1) * 4, st>>>(wb, g->nx, g->ny);
             done();
             mark(HULL_PROF_WALK);
-            k_walk_tiles<<<walk_grid, kTileThreads, tile_bytes, s>>>(wb, g->nx, g->ny);
+            k_walk_tiles<<<walk_grid, kTileThreads, tile_bytes, st>>>(wb, g->nx, g->ny);
             done();
+        }
+        // N and M: after the previous batch's reduce and overflow walk
+        if (s2 && bi > 0 && hipStreamWaitEvent(st, ev_acc, 0) != hipSuccess) rc = HULL_EDEVICE;
+        if (tile_ok) {
             dim3 rg((unsigned)((wb.slot_words / 4 + 255) / 256), (unsigned)wb.ntiles);
             mark(HULL_PROF_REDUCE);
-            k_reduce_tiles<<<rg, 256, 0, s>>>(wb, plane, N, M, stats);
+            k_reduce_tiles<<<rg, 256, 0, st>>>(wb, plane, N, M, stats);
             done();
         }
         mark(HULL_PROF_OVERFLOW);
-        k_walk_overflow<<<1024, 256, 0, s>>>(*h, h0, dg, wb, N, M, stats);
+        k_walk_overflow<<<1024, 256, 0, st>>>(*h, h0, dg, wb, N, M, stats);
         done();
-        const int rc = launch_status();
-        if (rc != HULL_OK) return rc;
+        if (s2 && hipEventRecord(ev_acc, st) != hipSuccess) rc = HULL_EDEVICE;
+        if (rc == HULL_OK) rc = launch_status();
     }
-    return launch_status();
+    if (s2) {
+        // the caller's stream covers every batch, also after an error, so that
+        // its completion still means the workspace is free
+        if (hipEventRecord(ev_join, s2) != hipSuccess || hipStreamWaitEvent(s, ev_join, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            if (rc == HULL_OK) rc = HULL_EDEVICE;
+        }
+        drop_events();
+    }
+    return rc == HULL_OK ? launch_status() : rc;
+}
+
+// Launch choices of the per-scan calls: the two-stream pass where it applies.
+CountOpts per_scan_opts()
+{
+    CountOpts o;
+    o.two_streams = true;
+    return o;
 }
 
 int run_msc_mask(const hullmi_grid *g, const int32_t *N, uint8_t *mask, int n_t, int mode, int nbr,
@@ -1034,7 +1135,7 @@ int hull_sc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_lo
             void *stream)
 {
     return sc_impl(hist, grid, wepl_low, N, mask, flags, stats, ws, ws_bytes, as_stream(stream),
-                   CountOpts{});
+                   per_scan_opts());
 }
 
 int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_low, int32_t n_t,
@@ -1042,7 +1143,7 @@ int hull_msc(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_l
              void *ws, size_t ws_bytes, void *stream)
 {
     return msc_impl(hist, grid, wepl_low, n_t, mode, nbr, N, mask, flags, stats, ws, ws_bytes,
-                    as_stream(stream), CountOpts{});
+                    as_stream(stream), per_scan_opts());
 }
 
 int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_high, int32_t frac_num,
@@ -1050,7 +1151,7 @@ int hull_sm(const hullmi_histories *hist, const hullmi_grid *grid, float wepl_hi
             uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
 {
     return sm_impl(hist, grid, wepl_high, frac_num, frac_den, mode, scope, nbr, M, mask, flags,
-                   stats, ws, ws_bytes, as_stream(stream), CountOpts{});
+                   stats, ws, ws_bytes, as_stream(stream), per_scan_opts());
 }
 
 int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi_params *p,
@@ -1058,7 +1159,7 @@ int hull_all(const hullmi_histories *hist, const hullmi_grid *grid, const hullmi
              uint32_t flags, hullmi_stats *stats, void *ws, size_t ws_bytes, void *stream)
 {
     return all_impl(hist, grid, p, N, M, sc_mask, msc_mask, sm_mask, flags, stats, ws, ws_bytes,
-                    as_stream(stream), CountOpts{});
+                    as_stream(stream), per_scan_opts());
 }
 
 // Sums the recorded event pairs per kernel (after the stream has finished).
@@ -1096,7 +1197,7 @@ int hull_count_profile(const hullmi_histories *hist, const hullmi_grid *grid,
 {
     if (!ms) return HULL_EINVAL;
     KernelProf prof;
-    CountOpts o;
+    CountOpts o = per_scan_opts();   // the batches of hull_all, one after another
     o.prof = &prof;
     const int rc = all_impl(hist, grid, p, N, M, nullptr, nullptr, nullptr, flags, stats, ws,
                             ws_bytes, as_stream(stream), o);

@@ -53,6 +53,10 @@ struct CountOpts {
     int ranges_per_group = 0;   // equal-work ranges per walk workgroup
     int length_classes = 0;     // line-length classes per slice (at most the default)
     int run_stride = 0;         // block stride of the item runs
+    // per-scan calls: a pass of several internal batches splits the workspace
+    // in two and alternates batches between the caller's stream and a second
+    // one (sequentially, in the same batches, when prof is set)
+    bool two_streams = false;
     KernelProf *prof = nullptr;  // event pairs around every launch
 };
 

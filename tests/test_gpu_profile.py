@@ -38,17 +38,18 @@ def test_count_profile_counts_and_launches():
 
 
 def test_count_profile_over_internal_batches():
-    """A workspace sized for 2^19 histories runs 2^20 + 1000 in three internal
-    batches: three launches of every counting kernel."""
-    spec = gen.config_spec(1, n_hist=(1 << 20) + 1000)
+    """The smallest workspace (2^16 histories: too small to split in two)
+    runs 300,000 histories in five internal batches on the caller's stream:
+    five launches of every counting kernel, and hull_all's counts."""
+    spec = gen.config_spec(1, n_hist=300_000)
     h = gen.generate(spec)
     hist = H.Histories.from_numpy(h, DEV)
     V = spec.grid.voxels
     N = torch.zeros(V, dtype=torch.int32, device=DEV)
     M = torch.zeros(V, dtype=torch.int32, device=DEV)
-    ws = H.workspace(H.HULL_OP_ALL, spec.grid, 1 << 19, DEV)
+    ws = H.workspace(H.HULL_OP_ALL, spec.grid, 1 << 16, DEV)
     prof = H.hull_count_profile(hist, spec.grid, H.make_params(), N, M, ws=ws)
-    assert all(n == 3 for _, n in prof.values())
+    assert all(n == 5 for _, n in prof.values())
     N2 = torch.zeros_like(N)
     M2 = torch.zeros_like(M)
     H.hull_all(hist, spec.grid, H.make_params(), N2, M2)

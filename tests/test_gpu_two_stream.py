@@ -1,0 +1,160 @@
+"""The two-stream counting pass of the per-scan calls: when the histories need
+more than one internal batch of the caller's workspace, the workspace is split
+in two halves and batches of equal size that fit a half alternate between the
+caller's stream and a second, library-owned stream; the reduce and overflow
+walk of each batch (which add into N and M) wait for the previous batch's.
+Counts are integers, so the result is the oracle's whatever the overlap
+(crossing counts of Sections 3.3 and 3.4; masks of Algorithms 1-3)."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from paper_1402_1720_amd import hullmi as H
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+N_HIST = (1 << 20) + 1000
+WS_FOR = 1 << 19
+
+
+def batch_plan(grid, n, ws_for):
+    """Internal batches of a per-scan hull_all call given a workspace of
+    hull_workspace_bytes(HULL_OP_ALL, grid, ws_for): (batch size, batches,
+    two streams). The library's rule, restated: the largest batch (at most
+    2^26, at least 2^16 histories) whose counting workspace fits; when that
+    does not hold every history, the largest that fits half of it, evened out
+    over the batches and rounded up to whole classification blocks of 8192."""
+    tot = H.hull_workspace_bytes(H.HULL_OP_ALL, grid, ws_for)
+    avail = H.hull_workspace_bytes(H.HULL_OP_SC, grid, ws_for)   # the counting part
+    assert tot > avail
+
+    def fits(b, room):
+        return H.hull_workspace_bytes(H.HULL_OP_SC, grid, b) <= room
+
+    def largest(room):
+        hi = max(1, min(n, 1 << 26))
+        if fits(hi, room):
+            return hi
+        lo = max(1, min(n, 1 << 16))
+        if not fits(lo, room):
+            return 0
+        while hi - lo > 1:
+            m = (lo + hi) // 2
+            lo, hi = (m, hi) if fits(m, room) else (lo, m)
+        return lo
+
+    B = largest(avail)
+    if n <= B:
+        return B, 1, False
+    B2 = largest(avail // 2 // 256 * 256)
+    if B2 == 0:
+        return B, -(-n // B), False
+    nbat = -(-n // B2)
+    Bw = min(B2, -(-(-(-n // nbat)) // 8192) * 8192)
+    return Bw, -(-n // Bw), True
+
+
+@pytest.fixture(scope="module")
+def case():
+    spec = gen.config_spec(1, n_hist=N_HIST)
+    h = gen.generate(spec)
+    G = oracle.grid_of(spec.grid)
+    rN, rM, rst = oracle.counts(h, G, 1.0, 5.0)
+    return spec, h, G, rN, rM, rst
+
+
+def test_the_workspace_splits_into_two_streams(case):
+    spec = case[0]
+    B, nbat, two = batch_plan(spec.grid, N_HIST, WS_FOR)
+    assert two and nbat >= 4 and B % 8192 == 0, (B, nbat)
+
+
+def test_two_stream_pass_equals_the_oracle(case):
+    spec, h, G, rN, rM, rst = case
+    hist = H.Histories.from_numpy(h, DEV)
+    V = spec.grid.voxels
+    ws = H.workspace(H.HULL_OP_ALL, spec.grid, WS_FOR, DEV)
+    side = torch.cuda.Stream()
+    for stream in (None, side):
+        N = torch.full((V,), 7, dtype=torch.int32, device=DEV)   # zeroed by the call
+        M = torch.full((V,), 7, dtype=torch.int32, device=DEV)
+        sc, msc, sm = (torch.empty(V, dtype=torch.uint8, device=DEV) for _ in range(3))
+        st = torch.zeros(6, dtype=torch.int64, device=DEV)
+        H.hull_all(hist, spec.grid, H.make_params(), N, M, sc, msc, sm, stats=st, ws=ws, stream=stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(N.cpu().numpy(), rN) and np.array_equal(M.cpu().numpy(), rM)
+        assert H.stats_dict(st) == rst
+        assert np.array_equal(sc.cpu().numpy(), oracle.sc(rN))
+        assert np.array_equal(msc.cpu().numpy(), oracle.msc(rN, G, 5))
+        assert np.array_equal(sm.cpu().numpy(), oracle.sm(rM, G, 3, 5)[0])
+        # a second pass accumulating into the same volumes
+        H.hull_all(hist, spec.grid, H.make_params(), N, M, flags=H.HULL_ACCUMULATE, ws=ws,
+                   stream=stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(N.cpu().numpy(), 2 * rN) and np.array_equal(M.cpu().numpy(), 2 * rM)
+
+
+def test_two_stream_single_rule_calls(case):
+    spec, h, G, rN, rM, _ = case
+    hist = H.Histories.from_numpy(h, DEV)
+    V = spec.grid.voxels
+    ws = H.workspace(H.HULL_OP_ALL, spec.grid, WS_FOR, DEV)
+    N, M = (torch.zeros(V, dtype=torch.int32, device=DEV) for _ in range(2))
+    mask = torch.empty(V, dtype=torch.uint8, device=DEV)
+    H.hull_sc(hist, spec.grid, 1.0, N, mask, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(N.cpu().numpy(), rN)
+    assert np.array_equal(mask.cpu().numpy(), oracle.sc(rN))
+    N.fill_(3)
+    H.hull_msc(hist, spec.grid, 1.0, 5, H.HULL_MSC_COUNT, H.HULL_NBR_INPLANE4, N, mask, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(N.cpu().numpy(), rN)
+    assert np.array_equal(mask.cpu().numpy(), oracle.msc(rN, G, 5))
+    H.hull_sm(hist, spec.grid, 5.0, 3, 5, H.HULL_SM_FRACTION, H.HULL_SCOPE_VOLUME,
+              H.HULL_NBR_INPLANE4, M, mask, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(M.cpu().numpy(), rM)
+    assert np.array_equal(mask.cpu().numpy(), oracle.sm(rM, G, 3, 5)[0])
+
+
+def test_count_profile_runs_the_same_batches(case):
+    """hull_count_profile runs the batches of the two-stream pass one after
+    another on the caller's stream (an event pair around each launch)."""
+    spec, h, _, rN, rM, _ = case
+    hist = H.Histories.from_numpy(h, DEV)
+    V = spec.grid.voxels
+    ws = H.workspace(H.HULL_OP_ALL, spec.grid, WS_FOR, DEV)
+    N, M = (torch.zeros(V, dtype=torch.int32, device=DEV) for _ in range(2))
+    prof = H.hull_count_profile(hist, spec.grid, H.make_params(), N, M, ws=ws)
+    _, nbat, _ = batch_plan(spec.grid, N_HIST, WS_FOR)
+    assert all(n == nbat for _, n in prof.values()), prof
+    assert np.array_equal(N.cpu().numpy(), rN) and np.array_equal(M.cpu().numpy(), rM)
+
+
+def test_captured_pass_stays_on_one_stream(case):
+    """Under graph capture the pass keeps to the capturing stream (same
+    batches as without the split); every replay, with eager work and a
+    synchronisation between replays, gives the oracle's counts."""
+    spec, h, _, rN, rM, _ = case
+    hist = H.Histories.from_numpy(h, DEV)
+    V = spec.grid.voxels
+    ws = H.workspace(H.HULL_OP_ALL, spec.grid, WS_FOR, DEV)
+    N, M = (torch.zeros(V, dtype=torch.int32, device=DEV) for _ in range(2))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):   # warm-up outside the capture
+        H.hull_all(hist, spec.grid, H.make_params(), N, M, ws=ws, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        H.hull_all(hist, spec.grid, H.make_params(), N, M, ws=ws, stream=s)
+    torch.cuda.synchronize()
+    for r in range(3):
+        N.fill_(11)
+        M.fill_(11)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(N.cpu().numpy(), rN), r
+        assert np.array_equal(M.cpu().numpy(), rM), r

@@ -1,9 +1,11 @@
 """Full-scale parity: the 256x256x64 scan (0.78125 x 0.78125 x 2.5 mm voxels)
 with 2e8 histories at 360 gantry angles, WEPL noise 3 mm and 2% uniform
 outliers, resident on the device and counted by one hull_all call in the
-launch configuration the benchmark times: three internal batches (2^26, 2^26
-and 65,782,272 histories) accumulating into one N and one M, one walk
-workgroup per CU with eight coarse ranges each, 259-counter tile rows.
+launch configuration the benchmark times: seven internal batches of
+28,573,696 histories (the last 28,557,824), alternating between the caller's
+stream and the library's second stream and accumulating into one N and one M,
+one walk workgroup per CU with eight coarse ranges each, 259-counter tile
+rows.
 
 The oracle counts the same histories chunk by chunk on the host (counts are
 integers, so chunking cannot change them; the oracle's own chunking pin fixes
