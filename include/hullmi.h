@@ -472,7 +472,9 @@ typedef struct hullmi_job {
  *   fills it; never more than 2048 / walk workgroups);
  * length_classes: line-length classes per z-slice by which the walk's items
  *   are grouped so that a wavefront walks lines of similar length (0..16;
- *   0 = 16, or fewer on grids of more than 128 slices);
+ *   0 = 16, or fewer on grids of more than 128 slices); with two or more, the
+ *   last class holds the lines that may pass through a voxel corner, which
+ *   need the walk's longer loop;
  * run_stride: the item runs of one (class, slice, length) bin are ordered
  *   by classification block modulo this stride, so that neighbouring runs
  *   come from histories of different gantry angles (0..256; 0 = the internal

@@ -183,7 +183,14 @@ inline bool tile_fits(const hullmi_grid *g)
 inline int length_classes(const hullmi_grid *g) { return std::max(1, std::min(16, 2048 / g->nz)); }
 
 // Length-class width (voxels of in-plane extent) for nl classes per slice.
-inline int length_width(const hullmi_grid *g, int nl) { return std::max(1, (g->nx + g->ny + nl - 1) / nl); }
+// Width of a length class in voxels: the last of the nl classes holds the
+// lines that may meet a voxel corner, the other nl - 1 split the lengths up
+// to nx + ny (a single class holds every line).
+inline int length_width(const hullmi_grid *g, int nl)
+{
+    const int m = nl > 1 ? nl - 1 : 1;
+    return std::max(1, (g->nx + g->ny + m - 1) / m);
+}
 
 // Runs of a sub-bin are ordered by classification block modulo a stride r,
 // so that neighbouring runs come from blocks r apart. By default r is the

@@ -135,6 +135,17 @@ __device__ __forceinline__ int length_class(const LineSlab &b, float rdz, int k,
     return c > 0.0f ? (int)c : 0;
 }
 
+// Whether the walk cannot rule out a voxel corner on the line's projection
+// (the state flag the set-up writes, from the line alone): d is even, i.e. the
+// x and y steps have the same sign, and the corner test cannot clear it.
+// Nearly all such lines come from the gantry angles along the grid axes,
+// where a line starts on a grid face and spans whole voxels in x or y.
+__device__ __forceinline__ bool may_meet_corner(const int q[6])
+{
+    const int32_t dx = q[3] - q[0], dy = q[4] - q[1];
+    return ((dx < 0) == (dy < 0)) && !corner_free(q[0], q[1], dx, dy);
+}
+
 // Quantised endpoints of history i (batch-relative index into h, whose
 // arrays start at h0): kGeoOk or the reason the history is skipped. c, s and
 // bits cache the cosine and sine of the last angle seen (histories come in
@@ -246,8 +257,13 @@ k_bin_classify(hullmi_histories h, int64_t h0, int64_t nb, DevGrid g, float e_lo
                             rec = pack_line(q);
                             const float rdz = sb.d[2] != 0.0f ? __builtin_amdgcn_rcpf(sb.d[2]) : 0.0f;
                             const float rlw = __builtin_amdgcn_rcpf((float)w.lwidth);
+                            // a line that may pass through a voxel corner makes its
+                            // whole wave take the longer walk loop: such lines get
+                            // the last length class to themselves
+                            const int corner_cls = may_meet_corner(q) ? w.nl - 1 : -1;
                             for (int k = k0; k <= k1; ++k) {
-                                const int lc = length_class(sb, rdz, k, w.nl, rlw);
+                                const int lc = corner_cls >= 0 ? corner_cls
+                                                               : length_class(sb, rdz, k, w.nl - 1, rlw);
                                 lp |= (uint32_t)lc << (4 * (k - k0));
                                 atomicAdd(&lh[(cls * w.nz + k) * w.nl + lc], 1u);
                             }
