@@ -82,6 +82,7 @@ def test_two_stream_pass_equals_the_oracle(case):
         M = torch.full((V,), 7, dtype=torch.int32, device=DEV)
         sc, msc, sm = (torch.empty(V, dtype=torch.uint8, device=DEV) for _ in range(3))
         st = torch.zeros(6, dtype=torch.int64, device=DEV)
+        torch.cuda.synchronize()   # the fills above ran on torch's stream
         H.hull_all(hist, spec.grid, H.make_params(), N, M, sc, msc, sm, stats=st, ws=ws, stream=stream)
         torch.cuda.synchronize()
         assert np.array_equal(N.cpu().numpy(), rN) and np.array_equal(M.cpu().numpy(), rM)
@@ -158,3 +159,42 @@ def test_captured_pass_stays_on_one_stream(case):
         torch.cuda.synchronize()
         assert np.array_equal(N.cpu().numpy(), rN), r
         assert np.array_equal(M.cpu().numpy(), rM), r
+
+
+def test_two_host_threads_share_the_second_stream(case):
+    """Two host threads run split passes at the same time, each on its own
+    stream with its own workspace and volumes; both share the library's
+    second stream and both get the oracle's counts, three times over."""
+    import threading
+    spec, h, _, rN, rM, rst = case
+    hist = H.Histories.from_numpy(h, DEV)
+    V = spec.grid.voxels
+    torch.cuda.synchronize()
+    results, errors = {}, []
+
+    def run(tid):
+        try:
+            s = torch.cuda.Stream()
+            ws = H.workspace(H.HULL_OP_ALL, spec.grid, WS_FOR, DEV)
+            out = []
+            for _ in range(3):
+                with torch.cuda.stream(s):   # allocated and cleared on the call's stream
+                    N, M = (torch.zeros(V, dtype=torch.int32, device=DEV) for _ in range(2))
+                    st = torch.zeros(6, dtype=torch.int64, device=DEV)
+                H.hull_all(hist, spec.grid, H.make_params(), N, M, stats=st, ws=ws, stream=s)
+                s.synchronize()
+                out.append((N.cpu().numpy(), M.cpu().numpy(), H.stats_dict(st)))
+            results[tid] = out
+        except Exception as e:   # reported in the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=run, args=(t,)) for t in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    assert sorted(results) == [0, 1]
+    for out in results.values():
+        for gN, gM, gst in out:
+            assert np.array_equal(gN, rN) and np.array_equal(gM, rM) and gst == rst
