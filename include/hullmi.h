@@ -180,8 +180,11 @@ const char *hull_strerror(int status);
  * HULL_OP_FBP_CUT or HULL_OP_SC_BINNED, where it gives the bins).
  * Returns 0 when nothing is needed, or (size_t)-1 on invalid arguments.
  * The counting ops (SC, MSC, SM, ALL) take their histories in internal
- * batches of at most 2^26: this is the size for batches of min(n, 2^26),
- * about 150 bytes per history on large scans. They also run in any smaller
+ * batches of at most 2^26: for n <= 2^26 this is the size for one batch of
+ * n, about 150 bytes per history on large scans; above 2^26, the size for two
+ * halves that each hold a batch of n / k histories (k the smallest even
+ * number of batches of at most 2^25), which the two-stream pass below takes
+ * two at a time. They also run in any smaller
  * workspace of at least hull_workspace_bytes(op, grid, min(n, 65536)), in
  * smaller batches (the largest that fit): the same results, with more
  * launches. When the histories need more than one batch of the workspace

@@ -281,8 +281,21 @@ size_t bin_ws_bytes(const hullmi_grid *g, int64_t B)
     return bytes;
 }
 
-// Counting workspace for n histories in the largest internal batches.
-size_t counts_ws_bytes(const hullmi_grid *g, int64_t n) { return bin_ws_bytes(g, batch_of(n, kBatch)); }
+// Counting workspace for n histories: one batch of all of them up to kBatch;
+// above that, two halves, each for a batch of n / k histories (rounded up to
+// whole classification blocks), k the smallest even number of batches of at
+// most kBatch / 2, which the per-scan calls' two-stream pass alternates
+// between its streams. On the 256x256x64 grid with 2e8 histories that is six
+// batches of 33.3M in about the 10.2 GB one batch of 2^26 takes; seven
+// batches (halves of one 2^26 batch's workspace) took 0.35 ms longer per pass.
+size_t counts_ws_bytes(const hullmi_grid *g, int64_t n)
+{
+    if (n <= kBatch) return bin_ws_bytes(g, batch_of(n, kBatch));
+    int64_t k = (n + kBatch / 2 - 1) / (kBatch / 2);
+    k += k & 1;
+    const int64_t b = ((n + k - 1) / k + kHistPerBlock - 1) / kHistPerBlock * kHistPerBlock;
+    return 2 * align_up(bin_ws_bytes(g, b)) + kAlign;
+}
 
 // The smallest counting workspace that n histories can run in.
 size_t counts_ws_min_bytes(const hullmi_grid *g, int64_t n)

@@ -45,10 +45,17 @@ def test_workspace_sizes():
     assert sc > 100 * 24                       # quantised endpoints at least
     assert H.hull_workspace_bytes(H.HULL_OP_MSC, g, 100) == sc
     assert H.hull_workspace_bytes(H.HULL_OP_ALL, g, 100) >= sc + 8 * 4
-    # the internal batch caps the workspace: 2^26 histories at most
+    # up to 2^26 histories, one internal batch of all of them
     big = H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 26)
-    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 31 - 1) == big
     assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 26 - 2 ** 16) < big
+    # above, two halves, each for a batch of n / k histories in whole blocks of
+    # 8192, k the smallest even number of batches of at most 2^25
+    def half(b):
+        return (H.hull_workspace_bytes(H.HULL_OP_SC, g, b) + 255) // 256 * 256
+    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 31 - 1) == 2 * half(2 ** 25) + 256   # k = 64
+    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 3 * 2 ** 25) == 2 * half(3 * 2 ** 23) + 256   # k = 4
+    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 26 + 1) == 2 * half(2 ** 24 + 8192) + 256   # k = 4
+    assert H.hull_workspace_bytes(H.HULL_OP_SC, g, 2 ** 31 - 1) < 2 * big
     f = H.hullmi_fbp_params(2000.0, 1.0, 5.0, -150.0, -55.0, 300, 22, 180, 0.0, 2.0, 0, 0.6)
     nb = 300 * 22 * 180
     assert H.hull_workspace_bytes(H.HULL_OP_FBP, g, 100, f) >= nb * 16

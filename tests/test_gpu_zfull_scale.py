@@ -1,8 +1,8 @@
 """Full-scale parity: the 256x256x64 scan (0.78125 x 0.78125 x 2.5 mm voxels)
 with 2e8 histories at 360 gantry angles, WEPL noise 3 mm and 2% uniform
 outliers, resident on the device and counted by one hull_all call in the
-launch configuration the benchmark times: seven internal batches of
-28,573,696 histories (the last 28,557,824), alternating between the caller's
+launch configuration the benchmark times: six internal batches of
+33,341,440 histories (the last 33,292,800), alternating between the caller's
 stream and the library's second stream and accumulating into one N and one M,
 one walk workgroup per CU with eight coarse ranges each, 259-counter tile
 rows.
