@@ -526,7 +526,10 @@ __device__ __forceinline__ bool slice_entry_i24(const int32_t P[3], const int32_
     bool ok = true;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        ok &= !((D[b] == 0) & ((P[b] < 0) | (P[b] >= kQ * n[b])));
+        // an axis the line does not move along must hold the point; the
+        // reversed line from the other endpoint has the same such axes, at the
+        // same coordinates, so only the first call (check_z) tests them
+        if (check_z) ok &= !((D[b] == 0) & ((P[b] < 0) | (P[b] >= kQ * n[b])));
         A[b] = D[b] < 0 ? -D[b] : D[b];
         en[b] = D[b] > 0 ? -P[b] : P[b] - kQ * n[b];
         g[b] = D[b] < 0;
@@ -543,28 +546,29 @@ __device__ __forceinline__ bool slice_entry_i24(const int32_t P[3], const int32_
         aw = take ? A[b] : aw;
         gw = take ? g[b] : gw;
     }
+    // The entry point's coordinate on a non-entry axis is num / den with den =
+    // 1024 aw; the voxel is floor(num / den), or ceil(num / den) - 1 =
+    // floor((num - 1) / den) where the walk steps down (up). With a = num or
+    // num - 1, it lies in [0, n) exactly when a >= 0 and floor(a / 1024) < n aw
+    // (the half-open range test on num, [0, n den) or (0, n den], restated).
     if (check_z) {
-        const int64_t num = mul_i24(P[2], aw) + mul_i24(D[2], ew);
-        const int64_t lim = (int64_t)aw << 10;
         const bool up = (gw != 0) & (D[2] < 0);
-        const bool bad = (up & ((num <= 0) | (num > lim))) | (!up & ((num < 0) | (num >= lim)));
+        const int64_t a = mul_i24(P[2], aw) + mul_i24(D[2], ew) - (up ? 1 : 0);
+        const bool bad = (a < 0) | ((a >> 10) >= (int64_t)aw);
         ok &= !((wa != 2) & (D[2] != 0) & bad);
     }
     const float raw = __builtin_amdgcn_rcpf((float)aw);
     int c[2];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-        const int64_t num = mul_i24(P[b], aw) + mul_i24(D[b], ew);
-        const int64_t lim = mul_i24(n[b], aw) << 10;
         const bool up = (gw != 0) & (D[b] < 0);
-        const bool bad = (up & ((num <= 0) | (num > lim))) | (!up & ((num < 0) | (num >= lim)));
-        // up: ceil(num / den) - 1 = floor((num - 1) / den); clamped into
-        // [0, lim) so that lanes whose line misses compute in range too
-        int64_t a = up ? num - 1 : num;
-        a = a < 0 ? 0 : (a >= lim ? lim - 1 : a);
-        const uint32_t m = (uint32_t)(a >> 10);   // below n aw <= 2^32
-        int q = (int)((float)m * raw);
-        q = max(0, min(q, n[b] - 1));
+        const int64_t a = mul_i24(P[b], aw) + mul_i24(D[b], ew) - (up ? 1 : 0);
+        const bool bad = (a < 0) | ((a >> 10) >= mul_i24(n[b], aw));
+        // where the axis is in range, m = floor(a / 1024) < n aw <= 2^32; a
+        // lane whose line misses computes a bounded q that is never used
+        const uint32_t m = (uint32_t)(a >> 10);
+        int q = (int)fminf((float)m * raw, 4096.0f);
+        q = min(q, n[b] - 1);
         const uint32_t qa = mul_u24((uint32_t)q, (uint32_t)aw);   // q aw < n aw <= 2^32: exact
         q -= qa > m ? 1 : 0;
         q += mul_u24((uint32_t)(q + 1), (uint32_t)aw) <= m ? 1 : 0;
